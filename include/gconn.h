@@ -1,0 +1,207 @@
+/*
+ * gconn.h -- C ABI of the MI355X (gfx950) graph-connectivity library.
+ *
+ * Implements the connectivity design space of Hong, Dhulipala and Shun,
+ * "Exploring the Design Space of Static and Incremental Graph Connectivity
+ * Algorithms on GPUs" (PACT 2020): a sampling phase (k-out, hook-based, BFS),
+ * the most frequent label L_max, a finish phase over the vertices whose label
+ * is not L_max (union-find variants with CAS linking, Shiloach-Vishkin,
+ * Liu-Tarjan, label propagation) with on-the-fly or separate tree compression,
+ * label finalisation, spanning-forest recording, and incremental batches of
+ * edge insertions and connectivity queries.
+ *
+ * Conventions shared by every entry point
+ *  - Vertex ids are uint32 in [0, n) with n <= 0xFFFFFFFE (0xFFFFFFFF is the
+ *    "empty" sentinel of forest slots and hook arrays).  Edge counts are uint64.
+ *  - Every array argument named "device" is memory the caller allocated on the
+ *    current HIP device (hipMalloc, or a torch CUDA tensor); the library never
+ *    allocates device memory except where a function says so, and never frees
+ *    caller memory.  The caller keeps ownership of every buffer.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued on it and the call returns without waiting unless the function
+ *    says otherwise; results are valid once the stream has been synchronised.
+ *    Workspace contents are scratch: do not reuse a workspace on another
+ *    stream while a call using it may still run.
+ *  - Argument errors are detected on the host before anything is enqueued and
+ *    return GCONN_EINVAL (message in gconn_last_error()).  HIP launch errors
+ *    return GCONN_EDEVICE.  Nothing throws across the ABI.
+ *  - Self-loops and duplicate edges are allowed everywhere.  n == 0 or m == 0
+ *    is a valid input (labels are then the identity).
+ *  - CSR rows must be sorted ascending when a sampler that reads "the first"
+ *    edges of a vertex is used (k-out, hook-based); results are still exact if
+ *    they are not, only the sampled subset changes.
+ */
+#ifndef GCONN_H
+#define GCONN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gconn_status {
+  GCONN_OK = 0,
+  GCONN_EINVAL = -1,       /* bad argument (null pointer, id range, option)      */
+  GCONN_ENOMEM = -2,       /* caller workspace smaller than gconn_workspace_size */
+  GCONN_EDEVICE = -3,      /* HIP runtime / launch error                          */
+  GCONN_ENODEV = -4,       /* no HIP device, or not a gfx950 device               */
+  GCONN_EBUSY = -5,        /* admission refused (serving)                         */
+  GCONN_ETIMEOUT = -6,     /* bounded wait expired                                */
+  GCONN_EUNSUPPORTED = -7  /* option combination without a correct algorithm     */
+} gconn_status;
+
+/* Graph formats (Notation: COO edge array; CSR Offsets[n+1] + Edges[m]). */
+enum { GCONN_CSR = 0, GCONN_COO = 1 };
+
+/* Sampling phase (Sampling Algorithms; Appendix A.1). */
+enum {
+  GCONN_SAMPLE_NONE = 0,
+  GCONN_SAMPLE_KOUT = 1, /* union-find over k edges per vertex, then full compress */
+  GCONN_SAMPLE_HB = 2,   /* hook to the first neighbour, then first N edges of roots */
+  GCONN_SAMPLE_BFS = 3   /* direction-optimising BFS from the largest-degree vertex */
+};
+
+/* Finish (link) algorithm (Finish Algorithms; Appendix A.2-A.4). */
+enum {
+  GCONN_LINK_ASYNC = 0,   /* Union-Async: CAS the larger root onto the smaller     */
+  GCONN_LINK_HOOKS = 1,   /* Union-Hooks: CAS on a hooks array, then plain write   */
+  GCONN_LINK_EARLY = 2,   /* Union-Early: walk both paths, hook on reaching a root */
+  GCONN_LINK_REM_CAS = 3, /* Union-Rem-CAS: Rem's algorithm with CAS + splice rule */
+  GCONN_LINK_ECL = 4,     /* ECL-CC's rule: Union-Async, halving finds, separate
+                             full-compress pass                                    */
+  GCONN_LINK_SV = 5,      /* root-based Shiloach-Vishkin (writeMin + full shortcut) */
+  GCONN_LINK_LT = 6,      /* Liu-Tarjan rule set, variant in lt_variant            */
+  GCONN_LINK_LP = 7       /* label propagation                                     */
+};
+
+/* On-the-fly compression inside Find (Appendix A.2, find options). */
+enum {
+  GCONN_FIND_NAIVE = 0,    /* no compression                                 */
+  GCONN_FIND_SPLIT = 1,    /* path splitting with CAS (AtomicSplit)          */
+  GCONN_FIND_HALVE = 2,    /* path halving with CAS (AtomicHalve)            */
+  GCONN_FIND_COMPRESS = 3  /* full path compression (not for Union-Rem-CAS)  */
+};
+
+/* Splice rule of Union-Rem-CAS at a non-root (Appendix A.2, splice options). */
+enum { GCONN_SPLICE_SPLIT_ONE = 0, GCONN_SPLICE_HALVE_ONE = 1 };
+
+/* Liu-Tarjan variants, in the paper's order (Appendix A.4): connect rule
+ * C(onnect)/P(arentConnect)/E(xtendedConnect), update rule U(pdate)/R(ootUpdate),
+ * shortcut S(hortcut)/F(ullShortcut), optional A(lter). */
+enum {
+  GCONN_LT_CUSA = 0, GCONN_LT_CRSA, GCONN_LT_PUSA, GCONN_LT_PRSA, GCONN_LT_PUS, GCONN_LT_PRS,
+  GCONN_LT_EUSA, GCONN_LT_EUS, GCONN_LT_CUFA, GCONN_LT_CRFA, GCONN_LT_PUFA, GCONN_LT_PRFA,
+  GCONN_LT_PUF, GCONN_LT_PRF, GCONN_LT_EUFA, GCONN_LT_EUF, GCONN_LT_COUNT
+};
+
+/* A graph resident in device memory.
+ *  CSR: offsets[n+1] (uint32 or uint64, offsets_64 says which; offsets[0] = 0,
+ *       non-decreasing, offsets[n] = m) and nbrs[m]; a symmetric graph stores
+ *       every undirected edge in both rows (the paper's inputs are symmetrised).
+ *  COO: nbrs = src[m], dst[m]: one entry per undirected edge is enough. */
+typedef struct gconn_graph {
+  int32_t format;        /* GCONN_CSR or GCONN_COO                  */
+  int32_t offsets_64;    /* CSR only: 1 = uint64 offsets, 0 = uint32 */
+  uint32_t n;            /* number of vertices                       */
+  uint32_t reserved;
+  uint64_t m;            /* CSR entries, or COO edges                */
+  const void* offsets;   /* device, CSR only                         */
+  const uint32_t* nbrs;  /* device: CSR neighbours, or COO sources   */
+  const uint32_t* dst;   /* device: COO destinations (NULL for CSR)  */
+} gconn_graph;
+
+typedef struct gconn_options {
+  int32_t sample;        /* GCONN_SAMPLE_*                      (default KOUT)   */
+  int32_t link;          /* GCONN_LINK_*                        (default ASYNC)  */
+  int32_t find;          /* GCONN_FIND_*                        (default SPLIT)  */
+  int32_t splice;        /* GCONN_SPLICE_* (Union-Rem-CAS only) (default SPLIT_ONE) */
+  int32_t lt_variant;    /* GCONN_LT_* (GCONN_LINK_LT only)     (default PRF)    */
+  uint32_t k;            /* k-out: edges sampled per vertex     (default 2)      */
+  uint32_t hb_n;         /* hook-based: first N edges of roots  (default 4)      */
+  uint32_t lmax_samples; /* vertices sampled for L_max, 1..4096 (default 1024)   */
+  uint64_t seed;         /* seeds the L_max sample and random k-out choices      */
+  int32_t kout_random;   /* 0: first k edges; 1: first edge + k-1 uniform picks  */
+  int32_t validate;      /* 1: check the graph on the device first (synchronous) */
+  int32_t block;         /* threads per workgroup, multiple of 64, <= 1024 (256) */
+  int32_t reserved;
+} gconn_options;
+
+/* Counters filled when a stats pointer is passed (the call then synchronises
+ * the stream before returning).  Host memory. */
+typedef struct gconn_stats {
+  uint64_t sampled_edges;   /* neighbour entries read by the sampling phase     */
+  uint64_t active_vertices; /* vertices gathered for the finish (label != L_max) */
+  uint64_t finish_edges;    /* neighbour entries read by the finish (per round 1) */
+  uint64_t hooks;           /* successful root links (union-find rules)         */
+  uint64_t rounds;          /* SV / LT / LP rounds, or BFS levels               */
+  uint32_t lmax;            /* most frequent sampled label (0xFFFFFFFF: none)   */
+  uint32_t bfs_source;      /* BFS sampling source (0xFFFFFFFF: none)           */
+} gconn_stats;
+
+/* Fills *opt with the defaults listed above. */
+void gconn_options_default(gconn_options* opt);
+
+/* Bytes of device workspace gconn_cc / gconn_spanning_forest need for this
+ * graph and options (want_forest = 1 for the spanning forest; want_labels = 0
+ * when the forest call gets labels_out == NULL).  opt may be NULL (defaults). */
+gconn_status gconn_workspace_size(const gconn_graph* g, const gconn_options* opt, int want_forest,
+                                  int want_labels, size_t* bytes);
+
+/* Static connectivity (Alg. "GConn for Static Connectivity"): labels_out[v]
+ * (device, n entries, caller-owned) receives the minimum vertex id of v's
+ * component.  labels_out doubles as the parent array during the run.
+ * workspace: device, >= gconn_workspace_size(g, opt, 0, 1) bytes, 256-byte
+ * aligned.  COO input uses the finish phase only (sampling needs CSR).
+ * SV, LT and LP iterate with one host synchronisation per round. */
+gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspace,
+                      size_t workspace_bytes, const gconn_options* opt, gconn_stats* stats,
+                      void* stream);
+
+/* Spanning forest (Alg. "GConn for Spanning Forest"): for every vertex r that
+ * stops being a root, fu[r], fv[r] (device, n entries each) receive the input
+ * edge that linked it; other slots hold 0xFFFFFFFF.  Exactly n - c slots are
+ * filled (c = number of components).  labels_out (device, nullable) receives
+ * the canonical labels as in gconn_cc.  Root-based finishes only: union-find
+ * rules and SV (LT and LP return GCONN_EUNSUPPORTED). */
+gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t* fv,
+                                   uint32_t* labels_out, void* workspace, size_t workspace_bytes,
+                                   const gconn_options* opt, gconn_stats* stats, void* stream);
+
+/* Incremental connectivity (Alg. "GConn for Incremental Connectivity").
+ * The handle is host memory created by gconn_inc_create; it keeps the parent
+ * array `parent_buf` (device, n_max entries, caller-owned, must outlive the
+ * handle) and uses `workspace` (device, >= gconn_inc_workspace_size bytes,
+ * caller-owned, must outlive the handle).  If `initial` is non-NULL its graph
+ * (n <= n_max) is connected first with gconn_cc's pipeline.  Batches are
+ * totally ordered on the handle's stream: a query batch sees exactly the
+ * inserts enqueued before it.  A handle is not thread-safe. */
+typedef struct gconn_inc gconn_inc;
+
+gconn_status gconn_inc_workspace_size(uint32_t n_max, const gconn_graph* initial,
+                                      const gconn_options* opt, size_t* bytes);
+gconn_status gconn_inc_create(uint32_t n_max, uint32_t* parent_buf, const gconn_graph* initial,
+                              void* workspace, size_t workspace_bytes, const gconn_options* opt,
+                              void* stream, gconn_inc** out);
+/* Insert k edges (src[i], dst[i]) (device arrays, ids < n_max). */
+gconn_status gconn_inc_insert_batch(gconn_inc* h, const uint32_t* src, const uint32_t* dst,
+                                    uint64_t k, void* stream);
+/* out[i] (device, q bytes) = 1 iff a[i] and b[i] are connected, else 0. */
+gconn_status gconn_inc_query_batch(gconn_inc* h, const uint32_t* a, const uint32_t* b, uint64_t q,
+                                   uint8_t* out, void* stream);
+/* labels_out (device, n_max entries) = canonical labels of the current graph. */
+gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream);
+/* Frees the host handle only (no device memory is owned). */
+gconn_status gconn_inc_destroy(gconn_inc* h);
+
+const char* gconn_status_string(gconn_status s);
+/* Message for the most recent failure on the calling thread ("" if none). */
+const char* gconn_last_error(void);
+/* Library version string. */
+const char* gconn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCONN_H */

@@ -1,0 +1,341 @@
+// gconn_api.hip -- the extern "C" entry points declared in include/gconn.h:
+// host-side argument checks, workspace sizing, and the incremental handle.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "gconn_internal.hpp"
+
+namespace gconn {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+gconn_status fail(gconn_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+gconn_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return GCONN_EDEVICE;
+}
+
+bool is_union_find(int link) {
+  return link == GCONN_LINK_ASYNC || link == GCONN_LINK_HOOKS || link == GCONN_LINK_EARLY ||
+         link == GCONN_LINK_REM_CAS || link == GCONN_LINK_ECL;
+}
+
+gconn_status check_options(const gconn_options& o) {
+  if (o.sample < GCONN_SAMPLE_NONE || o.sample > GCONN_SAMPLE_BFS)
+    return fail(GCONN_EINVAL, "options.sample out of range");
+  if (o.link < GCONN_LINK_ASYNC || o.link > GCONN_LINK_LP)
+    return fail(GCONN_EINVAL, "options.link out of range");
+  if (o.find < GCONN_FIND_NAIVE || o.find > GCONN_FIND_COMPRESS)
+    return fail(GCONN_EINVAL, "options.find out of range");
+  if (o.splice < GCONN_SPLICE_SPLIT_ONE || o.splice > GCONN_SPLICE_HALVE_ONE)
+    return fail(GCONN_EINVAL, "options.splice out of range");
+  if (o.lt_variant < 0 || o.lt_variant >= GCONN_LT_COUNT)
+    return fail(GCONN_EINVAL, "options.lt_variant out of range");
+  if (o.link == GCONN_LINK_REM_CAS && o.find == GCONN_FIND_COMPRESS)
+    return fail(GCONN_EUNSUPPORTED,
+                "Union-Rem-CAS combines with FindNaive, FindSplit or FindHalve only");
+  if (o.k < 1 || o.k > 64) return fail(GCONN_EINVAL, "options.k must be in [1, 64]");
+  if (o.hb_n < 1 || o.hb_n > 1024) return fail(GCONN_EINVAL, "options.hb_n must be in [1, 1024]");
+  if (o.lmax_samples < 1 || o.lmax_samples > kMaxLmaxSamples)
+    return fail(GCONN_EINVAL, "options.lmax_samples must be in [1, 4096]");
+  if (o.block < 64 || o.block > 1024 || (o.block % 64) != 0)
+    return fail(GCONN_EINVAL, "options.block must be a multiple of 64 in [64, 1024]");
+  return GCONN_OK;
+}
+
+gconn_status check_device_ptr(const void* p, const char* name) {
+  if (!p) return fail(GCONN_EINVAL, std::string(name) + " is NULL");
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the query's error for a later launch check
+    return fail(GCONN_EINVAL, std::string(name) + " is not device-accessible memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged &&
+      attr.type != hipMemoryTypeHost && attr.type != hipMemoryTypeUnified)
+    return fail(GCONN_EINVAL, std::string(name) + " is not device-accessible memory");
+  return GCONN_OK;
+}
+
+gconn_status check_device_ready() {
+  static std::mutex mu;
+  static int checked[64] = {0};  // 0 unknown, 1 ok, -1 not gfx950
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GCONN_ENODEV, "no HIP device");
+  }
+  if (dev < 0 || dev >= 64) return fail(GCONN_ENODEV, "unexpected device index");
+  std::lock_guard<std::mutex> lock(mu);
+  if (checked[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GCONN_ENODEV, "hipGetDeviceProperties failed");
+    }
+    checked[dev] = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+  }
+  if (checked[dev] < 0) return fail(GCONN_ENODEV, "current device is not gfx950");
+  return GCONN_OK;
+}
+
+gconn_status check_graph(const gconn_graph* g) {
+  if (!g) return fail(GCONN_EINVAL, "graph is NULL");
+  if (g->format != GCONN_CSR && g->format != GCONN_COO)
+    return fail(GCONN_EINVAL, "graph.format must be GCONN_CSR or GCONN_COO");
+  if (g->n > 0xFFFFFFFEu) return fail(GCONN_EINVAL, "graph.n must be <= 0xFFFFFFFE");
+  if (g->format == GCONN_CSR) {
+    if (!g->offsets_64 && g->m > 0xFFFFFFFFull)
+      return fail(GCONN_EINVAL, "m exceeds uint32 offsets; pass uint64 offsets");
+    if (g->n > 0 || g->m > 0) GCONN_TRY(check_device_ptr(g->offsets, "graph.offsets"));
+    if (g->m > 0) GCONN_TRY(check_device_ptr(g->nbrs, "graph.nbrs"));
+  } else {
+    if (g->m > 0) {
+      GCONN_TRY(check_device_ptr(g->nbrs, "graph.nbrs (COO src)"));
+      GCONN_TRY(check_device_ptr(g->dst, "graph.dst"));
+    }
+  }
+  return GCONN_OK;
+}
+
+static gconn_status resolve_options(const gconn_options* opt, gconn_options* out) {
+  if (opt) *out = *opt;
+  else gconn_options_default(out);
+  return check_options(*out);
+}
+
+static gconn_status check_workspace(void* ws, size_t have, size_t need) {
+  if (have < need)
+    return fail(GCONN_ENOMEM, "workspace has " + std::to_string(have) + " bytes, needs " +
+                                  std::to_string(need));
+  GCONN_TRY(check_device_ptr(ws, "workspace"));
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(GCONN_EINVAL, "workspace must be 256-byte aligned");
+  return GCONN_OK;
+}
+
+}  // namespace gconn
+
+using namespace gconn;
+
+struct gconn_inc {
+  uint32_t n_max;
+  uint32_t* P;
+  uint32_t* H;
+  uint8_t* ws;
+  size_t ws_bytes;
+  gconn_options opt;
+};
+
+extern "C" {
+
+void gconn_options_default(gconn_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sample = GCONN_SAMPLE_KOUT;
+  o->link = GCONN_LINK_ASYNC;
+  o->find = GCONN_FIND_SPLIT;
+  o->splice = GCONN_SPLICE_SPLIT_ONE;
+  o->lt_variant = GCONN_LT_PRF;
+  o->k = 2;
+  o->hb_n = 4;
+  o->lmax_samples = 1024;
+  o->seed = 1;
+  o->kout_random = 0;
+  o->validate = 0;
+  o->block = 256;
+}
+
+gconn_status gconn_workspace_size(const gconn_graph* g, const gconn_options* opt, int want_forest,
+                                  int want_labels, size_t* bytes) {
+  clear_error();
+  if (!g || !bytes) return fail(GCONN_EINVAL, "graph or bytes is NULL");
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  if (g->format != GCONN_CSR && g->format != GCONN_COO)
+    return fail(GCONN_EINVAL, "graph.format must be GCONN_CSR or GCONN_COO");
+  *bytes = plan_workspace(*g, o, want_forest != 0, want_labels != 0).total;
+  return GCONN_OK;
+}
+
+gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspace,
+                      size_t workspace_bytes, const gconn_options* opt, gconn_stats* stats,
+                      void* stream) {
+  clear_error();
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  GCONN_TRY(check_device_ready());
+  GCONN_TRY(check_graph(g));
+  if (g->format == GCONN_COO) o.sample = GCONN_SAMPLE_NONE;
+  if (g->n > 0) GCONN_TRY(check_device_ptr(labels_out, "labels_out"));
+  const WsLayout L = plan_workspace(*g, o, false, true);
+  GCONN_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  return run_static(*g, labels_out, nullptr, nullptr, true, static_cast<uint8_t*>(workspace), L, o,
+                    stats, static_cast<hipStream_t>(stream));
+}
+
+gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t* fv,
+                                   uint32_t* labels_out, void* workspace, size_t workspace_bytes,
+                                   const gconn_options* opt, gconn_stats* stats, void* stream) {
+  clear_error();
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  if (o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP)
+    return fail(GCONN_EUNSUPPORTED,
+                "spanning forest needs a root-based finish: a union-find rule or SV");
+  GCONN_TRY(check_device_ready());
+  GCONN_TRY(check_graph(g));
+  if (g->format == GCONN_COO) o.sample = GCONN_SAMPLE_NONE;
+  if (g->n > 0) {
+    GCONN_TRY(check_device_ptr(fu, "fu"));
+    GCONN_TRY(check_device_ptr(fv, "fv"));
+    if (labels_out) GCONN_TRY(check_device_ptr(labels_out, "labels_out"));
+  }
+  const bool labels = labels_out != nullptr;
+  const WsLayout L = plan_workspace(*g, o, true, labels);
+  GCONN_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  uint32_t* P = labels ? labels_out : reinterpret_cast<uint32_t*>(ws + L.P);
+  return run_static(*g, P, fu, fv, labels, ws, L, o, stats, static_cast<hipStream_t>(stream));
+}
+
+gconn_status gconn_inc_workspace_size(uint32_t n_max, const gconn_graph* initial,
+                                      const gconn_options* opt, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(GCONN_EINVAL, "bytes is NULL");
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  size_t total = align_up(sizeof(Ctrl), 256);
+  if (o.link == GCONN_LINK_HOOKS) total += align_up(4ull * n_max + 1, 256);
+  if (initial) total += plan_workspace(*initial, o, false, true).total;
+  *bytes = total;
+  return GCONN_OK;
+}
+
+gconn_status gconn_inc_create(uint32_t n_max, uint32_t* parent_buf, const gconn_graph* initial,
+                              void* workspace, size_t workspace_bytes, const gconn_options* opt,
+                              void* stream, gconn_inc** out) {
+  clear_error();
+  if (!out) return fail(GCONN_EINVAL, "out is NULL");
+  *out = nullptr;
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  if (!is_union_find(o.link))
+    return fail(GCONN_EUNSUPPORTED, "incremental batches use a union-find rule");
+  if (n_max > 0xFFFFFFFEu) return fail(GCONN_EINVAL, "n_max must be <= 0xFFFFFFFE");
+  GCONN_TRY(check_device_ready());
+  if (n_max > 0) GCONN_TRY(check_device_ptr(parent_buf, "parent_buf"));
+  if (initial) {
+    GCONN_TRY(check_graph(initial));
+    if (initial->n > n_max) return fail(GCONN_EINVAL, "initial graph has more than n_max vertices");
+  }
+  size_t need = 0;
+  GCONN_TRY(gconn_inc_workspace_size(n_max, initial, &o, &need));
+  GCONN_TRY(check_workspace(workspace, workspace_bytes, need));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  size_t at = align_up(sizeof(Ctrl), 256);
+  uint32_t* H = nullptr;
+  if (o.link == GCONN_LINK_HOOKS) {
+    H = reinterpret_cast<uint32_t*>(ws + at);
+    at += align_up(4ull * n_max + 1, 256);
+  }
+  GCONN_TRY(launch_iota(parent_buf, n_max, s));
+  if (H) GCONN_TRY(launch_fill(H, 0xFFFFFFFFu, n_max, s));
+  if (initial && initial->n > 0) {
+    gconn_options io = o;
+    if (initial->format == GCONN_COO) io.sample = GCONN_SAMPLE_NONE;
+    const WsLayout L = plan_workspace(*initial, io, false, true);
+    GCONN_TRY(run_static(*initial, parent_buf, nullptr, nullptr, true, ws + at, L, io, nullptr, s));
+  }
+  gconn_inc* h = new (std::nothrow) gconn_inc;
+  if (!h) return fail(GCONN_EINVAL, "host allocation of the handle failed");
+  h->n_max = n_max;
+  h->P = parent_buf;
+  h->H = H;
+  h->ws = ws;
+  h->ws_bytes = workspace_bytes;
+  h->opt = o;
+  *out = h;
+  return GCONN_OK;
+}
+
+static gconn_status validate_ids(gconn_inc* h, const uint32_t* a, const uint32_t* b, uint64_t k,
+                                 hipStream_t s);
+
+gconn_status gconn_inc_insert_batch(gconn_inc* h, const uint32_t* src, const uint32_t* dst,
+                                    uint64_t k, void* stream) {
+  clear_error();
+  if (!h) return fail(GCONN_EINVAL, "handle is NULL");
+  if (k == 0) return GCONN_OK;
+  GCONN_TRY(check_device_ptr(src, "src"));
+  GCONN_TRY(check_device_ptr(dst, "dst"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->opt.validate) GCONN_TRY(validate_ids(h, src, dst, k, s));
+  return launch_insert(h->opt, h->P, h->H, src, dst, k, s);
+}
+
+gconn_status gconn_inc_query_batch(gconn_inc* h, const uint32_t* a, const uint32_t* b, uint64_t q,
+                                   uint8_t* out, void* stream) {
+  clear_error();
+  if (!h) return fail(GCONN_EINVAL, "handle is NULL");
+  if (q == 0) return GCONN_OK;
+  GCONN_TRY(check_device_ptr(a, "a"));
+  GCONN_TRY(check_device_ptr(b, "b"));
+  GCONN_TRY(check_device_ptr(out, "out"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->opt.validate) GCONN_TRY(validate_ids(h, a, b, q, s));
+  return launch_query(h->opt, h->P, a, b, q, out, s);
+}
+
+gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream) {
+  clear_error();
+  if (!h) return fail(GCONN_EINVAL, "handle is NULL");
+  if (h->n_max == 0) return GCONN_OK;
+  GCONN_TRY(check_device_ptr(labels_out, "labels_out"));
+  return launch_finalize(h->P, h->n_max, labels_out, static_cast<hipStream_t>(stream));
+}
+
+gconn_status gconn_inc_destroy(gconn_inc* h) {
+  clear_error();
+  delete h;
+  return GCONN_OK;
+}
+
+const char* gconn_status_string(gconn_status s) {
+  switch (s) {
+    case GCONN_OK: return "GCONN_OK";
+    case GCONN_EINVAL: return "GCONN_EINVAL: invalid argument";
+    case GCONN_ENOMEM: return "GCONN_ENOMEM: workspace too small";
+    case GCONN_EDEVICE: return "GCONN_EDEVICE: HIP error";
+    case GCONN_ENODEV: return "GCONN_ENODEV: no gfx950 device";
+    case GCONN_EBUSY: return "GCONN_EBUSY: admission refused";
+    case GCONN_ETIMEOUT: return "GCONN_ETIMEOUT: bounded wait expired";
+    case GCONN_EUNSUPPORTED: return "GCONN_EUNSUPPORTED: unsupported option combination";
+  }
+  return "unknown gconn_status";
+}
+
+const char* gconn_last_error(void) { return g_last_error.c_str(); }
+
+const char* gconn_version(void) { return "gconn-gfx950 0.1.0"; }
+
+}  // extern "C"
+
+static gconn_status validate_ids(gconn_inc* h, const uint32_t* a, const uint32_t* b, uint64_t k,
+                                 hipStream_t s) {
+  return validate_pairs(a, b, k, h->n_max, reinterpret_cast<Ctrl*>(h->ws), s);
+}

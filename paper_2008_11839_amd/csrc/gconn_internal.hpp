@@ -1,0 +1,125 @@
+// gconn_internal.hpp -- host-side shared declarations of the gconn library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <string>
+
+#include "../../include/gconn.h"
+
+namespace gconn {
+
+// Small-vertex threshold: vertices with at most this many edges are processed
+// by one lane; larger ones are cut into segments of kSeg edges, one wave each.
+constexpr uint32_t kSmallDeg = 32;
+constexpr uint32_t kSeg = 1024;
+constexpr uint32_t kMaxLmaxSamples = 4096;
+constexpr int kRoundsPerSync = 8;        // device-side early-exit rounds per host check
+constexpr uint32_t kRoundSlots = 64;     // ring of per-round "changed" flags
+constexpr uint64_t kMaxRounds = 1u << 24;
+
+// Device control block at the start of every workspace (zeroed per call by a
+// kernel, never by hipMemsetAsync, so a captured graph replays correctly).
+struct Ctrl {
+  uint32_t lmax;
+  uint32_t small_count;
+  uint32_t seg_count;
+  uint32_t done;
+  uint32_t err;
+  uint32_t bfs_source;
+  uint32_t comp_min;
+  uint32_t frontier_count[2];
+  uint32_t pad0;
+  unsigned long long edge_count;      // materialised finish edges (SV/LT/LP)
+  unsigned long long bfs_key;         // argmax-degree key
+  unsigned long long frontier_edges[2];
+  unsigned long long explored_edges;
+  unsigned long long stat_sampled;
+  unsigned long long stat_active;
+  unsigned long long stat_finish_edges;
+  unsigned long long stat_hooks;
+  uint32_t changed[kRoundSlots];
+};
+
+struct WsLayout {
+  size_t ctrl = 0;
+  size_t P = 0;       // parent array when the caller gives no labels buffer
+  size_t small = 0;   // active small-vertex list (uint32[n])
+  size_t segs = 0;    // heavy-vertex segments (uint2[seg_cap])
+  size_t hooks = 0;   // Union-Hooks claim array (uint32[n])
+  size_t prev = 0;    // round-start parents (SV, LT)
+  size_t esrc = 0;    // materialised edges (SV, LT, LP)
+  size_t edst = 0;
+  size_t visited = 0; // BFS bitmap
+  size_t fr_bits0 = 0, fr_bits1 = 0;  // BFS frontier bitmaps
+  size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
+  uint64_t seg_cap = 0;
+  uint64_t edge_cap = 0;
+  size_t total = 0;
+};
+
+// Thread-local error reporting.
+void set_error(const std::string& msg);
+void clear_error();
+gconn_status fail(gconn_status s, const std::string& msg);
+gconn_status hip_fail(hipError_t e, const char* what);
+
+#define GCONN_HIP(call)                                        \
+  do {                                                         \
+    hipError_t _e = (call);                                    \
+    if (_e != hipSuccess) return ::gconn::hip_fail(_e, #call); \
+  } while (0)
+
+#define GCONN_LAUNCHED(what)                                    \
+  do {                                                          \
+    hipError_t _e = hipGetLastError();                          \
+    if (_e != hipSuccess) return ::gconn::hip_fail(_e, what);   \
+  } while (0)
+
+#define GCONN_TRY(expr)                      \
+  do {                                       \
+    gconn_status _s = (expr);                \
+    if (_s != GCONN_OK) return _s;           \
+  } while (0)
+
+// Option / graph validation (host only; no device access).
+gconn_status check_options(const gconn_options& o);
+gconn_status check_graph(const gconn_graph* g);
+gconn_status check_device_ptr(const void* p, const char* name);
+gconn_status check_device_ready();
+bool is_union_find(int link);
+
+// Workspace planning for one static run.
+WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool forest, bool labels);
+
+// The static pipeline (sampling, L_max, finish, finalisation) on parent array
+// P (n entries).  fu/fv nullable (forest).  labels: write canonical labels into
+// P at the end (finalisation) when true.
+gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_t* fv,
+                        bool finalize, uint8_t* ws, const WsLayout& L, const gconn_options& o,
+                        gconn_stats* stats, hipStream_t s);
+
+// Incremental helpers implemented next to the static kernels.
+gconn_status launch_iota(uint32_t* P, uint32_t n, hipStream_t s);
+gconn_status launch_fill(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s);
+gconn_status launch_finalize(uint32_t* P, uint32_t n, uint32_t* labels, hipStream_t s);
+gconn_status launch_insert(const gconn_options& o, uint32_t* P, uint32_t* H, const uint32_t* src,
+                           const uint32_t* dst, uint64_t k, hipStream_t s);
+// Synchronous id check of a pair list (ids < n); uses ctrl as scratch.
+gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, uint32_t n,
+                            Ctrl* ctrl, hipStream_t s);
+gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a,
+                          const uint32_t* b, uint64_t q, uint8_t* out, hipStream_t s);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+inline uint32_t grid_for(uint64_t items, uint32_t block, uint32_t cap = 1u << 20) {
+  uint64_t g = (items + block - 1) / block;
+  if (g == 0) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+}  // namespace gconn

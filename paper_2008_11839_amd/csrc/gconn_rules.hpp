@@ -1,0 +1,259 @@
+// gconn_rules.hpp -- device-side find, splice and union rules on the parent
+// array P (gfx950, wave64).
+//
+// P[x] == x marks a root; every other P[x] points to a smaller id in the same
+// tree (Notation and Preliminaries: elements point to themselves or to a parent
+// with a smaller ID).  All rules are root-based: a CAS only ever turns a root
+// into a child, always of a smaller id, so no cycle can form.
+//
+// Memory model.  The eight XCDs of an MI355X each have a private L2, so a plain
+// load inside a retry loop could keep returning a stale line.  Every read of P
+// inside a find / union loop is therefore a relaxed agent-scope atomic load
+// (global_load ... sc1), and every write is an agent-scope atomic (CAS, min,
+// store).  Correctness never depends on a read being fresh: any value P[x] has
+// ever held is an ancestor of x in the current forest, and each CAS
+// re-validates; the coherent loads only guarantee progress.
+//
+// Readings of the appendix pseudocode (Appendix A.2, find / splice / union
+// algorithms) where it is garbled:
+//   * FindSplit / FindHalve re-read v = P[u], w = P[v] on every iteration and
+//     return v once v == w (as printed the loop never reloads them).
+//   * The union rules CAS the parent of the larger *root* p_u (not of the
+//     endpoint u), which is what "only performs links on roots" requires.
+//   * SplitAtomicOne / HalveAtomicOne act on r_u: v = P[r_u], w = P[v]; if
+//     v != w, CAS P[r_u] from v to w; return v (split) or w (halve).
+//   * FindCompress lowers each path entry with an atomic min, which keeps
+//     P[x] <= x and is safe against concurrent lowering.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gconn {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+enum FindRule : int { kFindNaive = 0, kFindSplit = 1, kFindHalve = 2, kFindCompress = 3 };
+enum SpliceRule : int { kSpliceSplitOne = 0, kSpliceHalveOne = 1 };
+enum UnionRule : int { kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnionRemCas = 3 };
+
+__device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// CAS *p: expected -> desired.  On failure `expected` receives the current value.
+__device__ __forceinline__ bool cas(uint32_t* p, uint32_t& expected, uint32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t amin(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-launch state shared by the rules.
+struct LinkCtx {
+  uint32_t* P;         // parent array
+  uint32_t* H;         // hooks array (Union-Hooks only), kEmpty = unclaimed
+  uint32_t* fu;        // spanning-forest slots (nullable)
+  uint32_t* fv;
+  unsigned long long* hooks;  // successful-link counter (nullable)
+};
+
+__device__ __forceinline__ void record_link(const LinkCtx& c, uint32_t root, uint32_t u,
+                                            uint32_t v) {
+  // A root is linked at most once (it never becomes a root again), so the slot
+  // write is uncontended.
+  if (c.fu) {
+    c.fu[root] = u;
+    c.fv[root] = v;
+  }
+  if (c.hooks) atomicAdd(c.hooks, 1ull);
+}
+
+// ------------------------------------------------------------------ finds
+template <int F>
+__device__ __forceinline__ uint32_t find(uint32_t* P, uint32_t u) {
+  if constexpr (F == kFindNaive) {
+    uint32_t x = u;
+    for (;;) {
+      uint32_t p = ld(&P[x]);
+      if (p == x) return x;
+      x = p;
+    }
+  } else if constexpr (F == kFindSplit) {
+    for (;;) {
+      uint32_t v = ld(&P[u]);
+      uint32_t w = ld(&P[v]);
+      if (v == w) return v;
+      uint32_t e = v;
+      cas(&P[u], e, w);
+      u = v;
+    }
+  } else if constexpr (F == kFindHalve) {
+    for (;;) {
+      uint32_t v = ld(&P[u]);
+      uint32_t w = ld(&P[v]);
+      if (v == w) return v;
+      uint32_t e = v;
+      u = cas(&P[u], e, w) ? w : e;  // follow the new P[u]
+    }
+  } else {  // kFindCompress
+    uint32_t r = u;
+    for (;;) {
+      uint32_t p = ld(&P[r]);
+      if (p == r) break;
+      r = p;
+    }
+    uint32_t x = u;
+    while (x != r) {
+      uint32_t old = amin(&P[x], r);
+      if (old <= r) break;
+      x = old;
+    }
+    return r;
+  }
+}
+
+// ------------------------------------------------------------------ unions
+// Union-Async (Appendix A.2): find both roots; CAS the larger root onto the
+// smaller; on failure the CAS result is the new parent of the former root and
+// the search resumes from there.
+template <int F>
+__device__ __forceinline__ bool union_async(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t pu = find<F>(c.P, u), pv = find<F>(c.P, v);
+  while (pu != pv) {
+    if (pu < pv) {
+      uint32_t t = pu;
+      pu = pv;
+      pv = t;
+    }
+    uint32_t e = pu;
+    if (cas(&c.P[pu], e, pv)) {
+      record_link(c, pu, u, v);
+      return true;
+    }
+    pu = find<F>(c.P, e);
+    pv = find<F>(c.P, pv);
+  }
+  return false;
+}
+
+// Union-Hooks (Appendix A.2): the race is decided by a CAS on H[p_u]; the
+// winner then writes P[p_u] without contention.  A loser follows the claimed
+// hook target instead of waiting for the winner's write (a lane of the same
+// wave may be that winner, and lanes of one wave make no independent progress).
+template <int F>
+__device__ __forceinline__ bool union_hooks(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t pu = find<F>(c.P, u), pv = find<F>(c.P, v);
+  while (pu != pv) {
+    if (pu < pv) {
+      uint32_t t = pu;
+      pu = pv;
+      pv = t;
+    }
+    uint32_t next = ld(&c.P[pu]);
+    if (next == pu) {
+      uint32_t h = kEmpty;
+      if (cas(&c.H[pu], h, pv)) {
+        st(&c.P[pu], pv);
+        record_link(c, pu, u, v);
+        return true;
+      }
+      next = h;  // pu is being linked under h
+    }
+    pu = find<F>(c.P, next);
+    pv = find<F>(c.P, pv);
+  }
+  return false;
+}
+
+// Union-Early (Appendix A.2): walk the two paths together, always advancing the
+// larger endpoint with a splitting step, and link it the moment it is a root.
+// Optional trailing finds compress both paths.
+template <int F>
+__device__ __forceinline__ bool union_early(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t pu = u, pv = v;
+  bool linked = false;
+  while (pu != pv) {
+    if (pu < pv) {
+      uint32_t t = pu;
+      pu = pv;
+      pv = t;
+    }
+    uint32_t z = ld(&c.P[pu]);
+    if (z == pu) {
+      uint32_t e = pu;
+      if (cas(&c.P[pu], e, pv)) {
+        record_link(c, pu, u, v);
+        linked = true;
+        break;
+      }
+      z = e;
+    }
+    uint32_t w = ld(&c.P[z]);
+    if (w != z) {
+      uint32_t e = z;
+      cas(&c.P[pu], e, w);
+    }
+    pu = w;
+  }
+  if constexpr (F != kFindNaive) {
+    find<F>(c.P, u);
+    find<F>(c.P, v);
+  }
+  return linked;
+}
+
+// Union-Rem-CAS (Appendix A.2): compare the parents of the two current nodes;
+// the side with the larger parent either is a root (CAS it onto the other
+// side's parent) or takes one splice step towards its root.
+template <int F, int S>
+__device__ __forceinline__ bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t ru = u, rv = v;
+  for (;;) {
+    uint32_t pru = ld(&c.P[ru]), prv = ld(&c.P[rv]);
+    if (pru == prv) return false;
+    if (pru < prv) {
+      uint32_t t = ru;
+      ru = rv;
+      rv = t;
+      t = pru;
+      pru = prv;
+      prv = t;
+    }
+    if (ru == pru) {
+      uint32_t e = ru;
+      if (cas(&c.P[ru], e, prv)) {
+        record_link(c, ru, u, v);
+        if constexpr (F != kFindNaive) {
+          find<F>(c.P, u);
+          find<F>(c.P, v);
+        }
+        return true;
+      }
+      continue;
+    }
+    uint32_t w = ld(&c.P[pru]);
+    if (w != pru) {
+      uint32_t e = pru;
+      cas(&c.P[ru], e, w);
+    }
+    ru = (S == kSpliceSplitOne) ? pru : w;
+  }
+}
+
+// Compile-time rule bundle.
+template <int U, int F, int S>
+struct Rule {
+  static constexpr int kUnion = U, kFind = F, kSplice = S;
+  __device__ __forceinline__ static bool unite(const LinkCtx& c, uint32_t u, uint32_t v) {
+    if constexpr (U == kUnionAsync) return union_async<F>(c, u, v);
+    else if constexpr (U == kUnionHooks) return union_hooks<F>(c, u, v);
+    else if constexpr (U == kUnionEarly) return union_early<F>(c, u, v);
+    else return union_rem_cas<F, S>(c, u, v);
+  }
+};
+
+}  // namespace gconn

@@ -1,0 +1,1295 @@
+// gconn_static.hip -- kernels and host pipeline of static connectivity and
+// spanning forest on gfx950 (Alg. "GConn for Static Connectivity" and
+// "GConn for Spanning Forest": init, sampling, L_max, finish, finalisation).
+//
+// Execution shape.  Streaming passes over the n vertices use one lane per
+// vertex in wave-uniform grid-stride loops (every lane of a wave runs the same
+// number of iterations, so wave-wide ballots, scans and shuffles are safe).
+// The finish phase first gathers the active vertices (label != L_max, degree
+// > 0; vertex gathering) into a small-vertex list, processed one lane per
+// vertex with its edges walked serially (the edge-reorganisation goal of no
+// same-vertex CAS conflicts inside a wave), and a heavy-vertex segment list,
+// one wave per segment of up to kSeg edges (load balancing of hubs).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "gconn_internal.hpp"
+#include "gconn_rules.hpp"
+
+namespace gconn {
+
+// --------------------------------------------------------------- helpers
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+
+// Wave-uniform iteration: returns the first vertex handled by this wave.
+__device__ __forceinline__ uint64_t wave_base() {
+  return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ull;
+}
+__device__ __forceinline__ uint64_t wave_stride() { return (uint64_t)gridDim.x * blockDim.x; }
+__device__ __forceinline__ uint64_t wave_index() {
+  return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+}
+__device__ __forceinline__ uint64_t wave_count() { return ((uint64_t)gridDim.x * blockDim.x) >> 6; }
+
+// All 64 lanes must be active.
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long x) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    unsigned long long y = __shfl_xor(x, d);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+// Exclusive prefix sum of cnt over the wave; *total receives the wave sum.
+__device__ __forceinline__ uint32_t wave_exclusive(uint32_t cnt, uint32_t* total) {
+  uint32_t x = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (lane() >= (uint32_t)d) x += y;
+  }
+  *total = __shfl(x, 63);
+  return x - cnt;
+}
+// Reserve cnt slots per lane in a global list; returns this lane's first slot.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t* counter, uint32_t cnt) {
+  uint32_t total;
+  uint32_t off = wave_exclusive(cnt, &total);
+  uint32_t base = 0;
+  if (total && lane() == 0) base = atomicAdd(counter, total);
+  base = __shfl(base, 0);
+  return base + off;
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t state0, uint64_t i) {
+  uint64_t z = state0 + (i + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t root_plain(const uint32_t* P, uint32_t x) {
+  uint32_t p = P[x];
+  while (p != x) {
+    x = p;
+    p = P[x];
+  }
+  return x;
+}
+
+// --------------------------------------------------------------- setup
+__global__ void k_ctrl_init(Ctrl* c) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(c);
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c->lmax = kEmpty;
+    c->bfs_source = kEmpty;
+    c->comp_min = kEmpty;
+  }
+}
+
+__global__ void k_iota(uint32_t* P, uint32_t n) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride())
+    P[v] = (uint32_t)v;
+}
+
+__global__ void k_fill(uint32_t* p, uint32_t value, uint64_t count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += wave_stride())
+    p[i] = value;
+}
+
+__global__ void k_init(uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride()) {
+    P[v] = (uint32_t)v;
+    if (fu) {
+      fu[v] = kEmpty;
+      fv[v] = kEmpty;
+    }
+  }
+}
+
+__global__ void k_copy(uint32_t* dst, const uint32_t* src, uint64_t count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += wave_stride())
+    dst[i] = src[i];
+}
+
+template <typename OffT>
+__global__ void k_validate_csr(const OffT* off, const uint32_t* nbrs, uint32_t n, uint64_t m,
+                               Ctrl* c) {
+  uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0 && (off[0] != 0 || (uint64_t)off[n] != m)) c->err = 1;
+  for (uint64_t v = tid; v < n; v += wave_stride())
+    if (off[v + 1] < off[v]) c->err = 1;
+  for (uint64_t e = tid; e < m; e += wave_stride())
+    if (nbrs[e] >= n) c->err = 1;
+}
+
+__global__ void k_validate_ids(const uint32_t* a, const uint32_t* b, uint64_t m, uint32_t n,
+                               Ctrl* c) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += wave_stride())
+    if (a[e] >= n || b[e] >= n) c->err = 1;
+}
+
+// --------------------------------------------------------------- sampling
+// k-out sampling (Sampling Algorithms; Appendix A.1): each vertex unites with
+// its first k neighbours (or its first neighbour plus k-1 uniform picks).  One
+// lane per vertex reads its leading neighbours together (CSR coalescing) and
+// runs its unions serially (edge reorganisation).
+template <class R, typename OffT>
+__global__ void k_sample_kout(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                              uint32_t n, uint32_t k, int random, uint64_t seed, LinkCtx lc,
+                              Ctrl* stats) {
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    uint64_t v = base + lane();
+    uint32_t take = 0;
+    if (v < n) {
+      uint64_t b = off[v], deg = (uint64_t)off[v + 1] - b;
+      take = (uint32_t)(deg < k ? deg : k);
+      if (!random) {
+        for (uint32_t j = 0; j < take; ++j) R::unite(lc, (uint32_t)v, nbrs[b + j]);
+      } else if (deg > 0) {
+        R::unite(lc, (uint32_t)v, nbrs[b]);
+        for (uint32_t j = 1; j < k; ++j) {
+          uint32_t r = (uint32_t)(splitmix64_at(seed, v * k + j) >> 32);
+          uint64_t pick = ((uint64_t)r * deg) >> 32;
+          R::unite(lc, (uint32_t)v, nbrs[b + pick]);
+        }
+        take = k;
+      }
+    }
+    if (stats) {
+      unsigned long long s = wave_sum(take);
+      if (lane() == 0 && s) atomicAdd(&stats->stat_sampled, s);
+    }
+  }
+}
+
+// Hook-based sampling, step 1 (Sampling Algorithms, HB): P[v] = min(v, w) for
+// the first (smallest) neighbour w; contention-free, one write per vertex.
+template <typename OffT>
+__global__ void k_hb_step1(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                           uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv, Ctrl* stats) {
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    uint64_t v = base + lane();
+    uint32_t took = 0;
+    if (v < n) {
+      uint64_t b = off[v];
+      if ((uint64_t)off[v + 1] > b) {
+        took = 1;
+        uint32_t w = nbrs[b];
+        if (w < v) {
+          P[v] = w;
+          if (fu) {
+            fu[v] = (uint32_t)v;
+            fv[v] = w;
+          }
+        }
+      }
+    }
+    if (stats) {
+      unsigned long long s = wave_sum(took);
+      if (lane() == 0 && s) atomicAdd(&stats->stat_sampled, s);
+    }
+  }
+}
+
+// HB step 2: vertices that stayed roots after step 1 (degree 0, or first
+// neighbour not smaller -- decided from the graph, not from P, so concurrent
+// links of step 2 cannot change the sampled set) unite with their first N
+// neighbours.
+template <class R, typename OffT>
+__global__ void k_hb_step2(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                           uint32_t n, uint32_t N, LinkCtx lc, Ctrl* stats) {
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    uint64_t v = base + lane();
+    uint32_t take = 0;
+    if (v < n) {
+      uint64_t b = off[v], deg = (uint64_t)off[v + 1] - b;
+      if (deg > 0 && nbrs[b] >= v) {
+        take = (uint32_t)(deg < N ? deg : N);
+        for (uint32_t j = 0; j < take; ++j) R::unite(lc, (uint32_t)v, nbrs[b + j]);
+      }
+    }
+    if (stats) {
+      unsigned long long s = wave_sum(take);
+      if (lane() == 0 && s) atomicAdd(&stats->stat_sampled, s);
+    }
+  }
+}
+
+// Full compression: P[v] = root(v) for all v (pointer jumping).  Runs after a
+// kernel boundary with no concurrent links, so plain loads are exact enough:
+// any value read is an ancestor.
+__global__ void k_compress(uint32_t* P, uint32_t* out, uint32_t n) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride()) {
+    uint32_t p = P[v];
+    uint32_t r = p;
+    if (p != v) r = root_plain(P, p);
+    if (out != P || r != p) out[v] = r;
+  }
+}
+
+// GetMostFrequentLabel over a seeded sample of vertices: sample j is vertex
+// floor(hi32(SplitMix64_j(seed)) * n / 2^32).  Counts go to an LDS hash table;
+// the winner is the largest count, smallest label on ties.
+constexpr uint32_t kLmaxTable = 2 * kMaxLmaxSamples;
+__global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, uint32_t samples,
+                                               uint64_t seed, Ctrl* c) {
+  __shared__ uint32_t keys[kLmaxTable];
+  __shared__ uint32_t cnts[kLmaxTable];
+  __shared__ unsigned long long best;
+  for (uint32_t i = threadIdx.x; i < kLmaxTable; i += blockDim.x) {
+    keys[i] = kEmpty;
+    cnts[i] = 0;
+  }
+  if (threadIdx.x == 0) best = 0;
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < samples; j += blockDim.x) {
+    uint32_t hi = (uint32_t)(splitmix64_at(seed, j) >> 32);
+    uint32_t v = (uint32_t)(((uint64_t)hi * n) >> 32);
+    uint32_t label = P[v];
+    uint32_t h = (label * 2654435761u) & (kLmaxTable - 1);
+    for (;;) {
+      uint32_t prev = atomicCAS(&keys[h], kEmpty, label);
+      if (prev == kEmpty || prev == label) {
+        atomicAdd(&cnts[h], 1u);
+        break;
+      }
+      h = (h + 1) & (kLmaxTable - 1);
+    }
+  }
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (uint32_t i = threadIdx.x; i < kLmaxTable; i += blockDim.x)
+    if (keys[i] != kEmpty) {
+      unsigned long long key = ((unsigned long long)cnts[i] << 32) | (kEmpty - keys[i]);
+      mine = key > mine ? key : mine;
+    }
+  mine = wave_max(mine);
+  if (lane() == 0) atomicMax(&best, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && best) c->lmax = kEmpty - (uint32_t)(best & 0xFFFFFFFFu);
+}
+
+// --------------------------------------------------------------- gathering
+// Vertex gathering: active = degree > 0 and label != L_max (L_max = kEmpty
+// when there was no sampling, so every vertex with edges is active).
+template <typename OffT>
+__global__ void k_gather(const OffT* __restrict__ off, const uint32_t* __restrict__ P, uint32_t n,
+                         Ctrl* c, uint32_t* small, uint2* segs, int want_stats) {
+  const uint32_t lmax = c->lmax;
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    uint64_t v = base + lane();
+    uint64_t deg = 0;
+    bool active = false;
+    if (v < n) {
+      deg = (uint64_t)off[v + 1] - off[v];
+      active = deg > 0 && P[v] != lmax;
+    }
+    bool is_small = active && deg <= kSmallDeg;
+    uint32_t nseg = (active && !is_small) ? (uint32_t)((deg + kSeg - 1) / kSeg) : 0;
+    uint32_t slot = wave_reserve(&c->small_count, is_small ? 1u : 0u);
+    if (is_small) small[slot] = (uint32_t)v;
+    uint32_t sbase = wave_reserve(&c->seg_count, nseg);
+    for (uint32_t t = 0; t < nseg; ++t) segs[sbase + t] = make_uint2((uint32_t)v, t);
+    if (want_stats) {
+      unsigned long long a = wave_sum(active ? 1 : 0), e = wave_sum(active ? deg : 0);
+      if (lane() == 0) {
+        if (a) atomicAdd(&c->stat_active, a);
+        if (e) atomicAdd(&c->stat_finish_edges, e);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- finish (union-find)
+// Alg. union-find meta-algorithm: every edge (u, v) of every active u is united.
+template <class R, typename OffT>
+__global__ void k_finish_small(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                               const uint32_t* __restrict__ small, const Ctrl* c, LinkCtx lc) {
+  const uint32_t count = c->small_count;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += wave_stride()) {
+    uint32_t u = small[i];
+    uint64_t b = off[u], e = off[u + 1];
+    for (uint64_t x = b; x < e; ++x) R::unite(lc, u, nbrs[x]);
+  }
+}
+
+template <class R, typename OffT>
+__global__ void k_finish_segs(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                              const uint2* __restrict__ segs, const Ctrl* c, LinkCtx lc) {
+  const uint32_t count = c->seg_count;
+  for (uint64_t s = wave_index(); s < count; s += wave_count()) {
+    uint2 sg = segs[s];
+    uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
+    uint64_t e = off[sg.x + 1];
+    if (e > b + kSeg) e = b + kSeg;
+    for (uint64_t x = b + lane(); x < e; x += 64) R::unite(lc, sg.x, nbrs[x]);
+  }
+}
+
+// COO finish (no sampling for COO): one lane per edge.
+template <class R>
+__global__ void k_unite_pairs(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                              uint64_t m, LinkCtx lc) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += wave_stride())
+    R::unite(lc, a[e], b[e]);
+}
+
+// --------------------------------------------------------------- materialised edges
+// SV, LT and LP iterate over the active edges many times; they are laid out
+// once as a COO pair list (one entry per CSR entry of an active vertex).
+template <typename OffT>
+__global__ void k_materialize_small(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                                    const uint32_t* __restrict__ small, Ctrl* c, uint32_t* esrc,
+                                    uint32_t* edst) {
+  const uint32_t count = c->small_count;
+  for (uint64_t base = wave_base(); base < count; base += wave_stride()) {
+    uint64_t i = base + lane();
+    uint32_t u = 0, deg = 0;
+    uint64_t b = 0;
+    if (i < count) {
+      u = small[i];
+      b = off[u];
+      deg = (uint32_t)((uint64_t)off[u + 1] - b);
+    }
+    uint32_t total;
+    uint32_t o = wave_exclusive(deg, &total);
+    unsigned long long pos = 0;
+    if (total && lane() == 0) pos = atomicAdd(&c->edge_count, (unsigned long long)total);
+    pos = __shfl(pos, 0) + o;
+    for (uint32_t j = 0; j < deg; ++j) {
+      esrc[pos + j] = u;
+      edst[pos + j] = nbrs[b + j];
+    }
+  }
+}
+
+template <typename OffT>
+__global__ void k_materialize_segs(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                                   const uint2* __restrict__ segs, Ctrl* c, uint32_t* esrc,
+                                   uint32_t* edst) {
+  const uint32_t count = c->seg_count;
+  for (uint64_t s = wave_index(); s < count; s += wave_count()) {
+    uint2 sg = segs[s];
+    uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
+    uint64_t e = off[sg.x + 1];
+    if (e > b + kSeg) e = b + kSeg;
+    unsigned long long pos = 0;
+    if (lane() == 0) pos = atomicAdd(&c->edge_count, (unsigned long long)(e - b));
+    pos = __shfl(pos, 0);
+    for (uint64_t x = b + lane(); x < e; x += 64) {
+      esrc[pos + (x - b)] = sg.x;
+      edst[pos + (x - b)] = nbrs[x];
+    }
+  }
+}
+
+__global__ void k_materialize_coo(const uint32_t* a, const uint32_t* b, uint64_t m, Ctrl* c,
+                                  uint32_t* esrc, uint32_t* edst) {
+  uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) c->edge_count = m;
+  for (uint64_t e = tid; e < m; e += wave_stride()) {
+    esrc[e] = a[e];
+    edst[e] = b[e];
+  }
+}
+
+// --------------------------------------------------------------- rounds (SV, LT, LP)
+// Rounds run K at a time between host checks.  round_begin decides on the
+// device whether the previous round changed anything; once a round makes no
+// change every later kernel of the batch returns at once.
+__global__ void k_round_begin(Ctrl* c, uint32_t r) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (r > 0 && c->changed[(r - 1) % kRoundSlots] == 0) c->done = 1;
+    c->changed[r % kRoundSlots] = 0;
+  }
+}
+
+__device__ __forceinline__ void mark_changed(Ctrl* c, uint32_t slot) {
+  __hip_atomic_store(&c->changed[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Shiloach-Vishkin round (Appendix A.3): for each edge, the larger of the two
+// labels, if it was a root at the start of the round, is lowered to the
+// smaller with writeMin.  snapshot = 1 reads both labels from the round-start
+// copy (used when recording a spanning forest).
+__global__ void k_sv_round(const uint32_t* __restrict__ esrc, const uint32_t* __restrict__ edst,
+                           Ctrl* c, uint32_t* P, const uint32_t* __restrict__ prev, uint32_t slot,
+                           int snapshot) {
+  if (c->done) return;
+  const uint64_t E = c->edge_count;
+  bool any = false;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += wave_stride()) {
+    uint32_t u = esrc[e], v = edst[e];
+    uint32_t pu = snapshot ? prev[u] : ld(&P[u]);
+    uint32_t pv = snapshot ? prev[v] : ld(&P[v]);
+    uint32_t l = pu < pv ? pu : pv, h = pu < pv ? pv : pu;
+    if (l != h && prev[h] == h) {
+      amin(&P[h], l);
+      any = true;
+    }
+  }
+  if (any) mark_changed(c, slot);
+}
+
+// Forest edge for SV: an edge whose round-start labels are {l, h} and whose
+// larger root h ended the hooking step at exactly l is a valid forest edge for
+// slot h; the first such edge claims the slot.
+__global__ void k_sv_record(const uint32_t* __restrict__ esrc, const uint32_t* __restrict__ edst,
+                            const Ctrl* c, const uint32_t* P, const uint32_t* __restrict__ prev,
+                            uint32_t* fu, uint32_t* fv) {
+  if (c->done) return;
+  const uint64_t E = c->edge_count;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += wave_stride()) {
+    uint32_t u = esrc[e], v = edst[e];
+    uint32_t pu = prev[u], pv = prev[v];
+    uint32_t l = pu < pv ? pu : pv, h = pu < pv ? pv : pu;
+    if (l != h && ld(&P[h]) == l) {
+      uint32_t x = kEmpty;
+      if (cas(&fu[h], x, u)) fv[h] = v;
+    }
+  }
+}
+
+// FullShortcut over every vertex, then prev = P (Shiloach-Vishkin round end;
+// Liu-Tarjan FullShortcut).  Changes count as progress for LT.
+__global__ void k_shortcut_full(Ctrl* c, uint32_t* P, uint32_t* prev, uint32_t n, uint32_t slot,
+                                int count_change) {
+  if (c->done) return;
+  bool any = false;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride()) {
+    uint32_t p = P[v];
+    uint32_t r = p;
+    if (p != v) r = root_plain(P, p);
+    if (r != p) {
+      P[v] = r;
+      any = true;
+    }
+    if (prev) prev[v] = r;
+  }
+  if (count_change && any) mark_changed(c, slot);
+}
+
+// Liu-Tarjan Shortcut: one pointer-jumping step, P[v] = P[P[v]].
+__global__ void k_shortcut_one(Ctrl* c, uint32_t* P, uint32_t* prev, uint32_t n, uint32_t slot) {
+  if (c->done) return;
+  bool any = false;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride()) {
+    uint32_t p = ld(&P[v]);
+    uint32_t g = ld(&P[p]);
+    if (g < p) {
+      amin(&P[v], g);
+      any = true;
+    }
+    if (prev) prev[v] = ld(&P[v]);
+  }
+  if (any) mark_changed(c, slot);
+}
+
+// Liu-Tarjan connect + update (Appendix A.4) with in-place atomic minimum:
+// connect 0 = Connect (endpoints to each other), 1 = ParentConnect (parents to
+// each other's parents), 2 = ExtendedConnect (parents to both endpoints and
+// both parents).  root_update = 1 applies a message only to a vertex that was a
+// root at the start of the round.
+__device__ __forceinline__ bool lt_send(uint32_t* P, const uint32_t* prev, uint32_t to,
+                                        uint32_t val, int root_update) {
+  if (root_update && prev[to] != to) return false;
+  return amin(&P[to], val) > val;
+}
+
+__global__ void k_lt_round(const uint32_t* __restrict__ esrc, const uint32_t* __restrict__ edst,
+                           Ctrl* c, uint32_t* P, const uint32_t* __restrict__ prev, uint32_t slot,
+                           int connect, int root_update) {
+  if (c->done) return;
+  const uint64_t E = c->edge_count;
+  bool any = false;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += wave_stride()) {
+    uint32_t v = esrc[e], w = edst[e];
+    if (v == kEmpty) continue;  // removed by Alter
+    if (connect == 0) {
+      any |= lt_send(P, prev, v, w, root_update);
+      any |= lt_send(P, prev, w, v, root_update);
+    } else {
+      uint32_t pv = ld(&P[v]), pw = ld(&P[w]);
+      if (pv == pw) continue;
+      any |= lt_send(P, prev, pv, pw, root_update);
+      any |= lt_send(P, prev, pw, pv, root_update);
+      if (connect == 2) {
+        any |= lt_send(P, prev, v, pw, root_update);
+        any |= lt_send(P, prev, w, pv, root_update);
+      }
+    }
+  }
+  if (any) mark_changed(c, slot);
+}
+
+// Liu-Tarjan Alter: replace each edge by the edge between its endpoints'
+// parents; an edge whose parents coincide is removed.
+__global__ void k_lt_alter(uint32_t* esrc, uint32_t* edst, Ctrl* c, const uint32_t* P,
+                           uint32_t slot) {
+  if (c->done) return;
+  const uint64_t E = c->edge_count;
+  bool any = false;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += wave_stride()) {
+    uint32_t v = esrc[e];
+    if (v == kEmpty) continue;
+    uint32_t w = edst[e];
+    uint32_t pv = P[v], pw = P[w];
+    if (pv == pw) {
+      esrc[e] = kEmpty;
+    } else if (pv != v || pw != w) {
+      esrc[e] = pv;
+      edst[e] = pw;
+      any = true;
+    }
+  }
+  if (any) mark_changed(c, slot);
+}
+
+// Label propagation round: across an edge with different labels the larger
+// label is lowered to the smaller.  After sampling, labels are compressed
+// pointers shared by a whole sampled component, and the vertices labelled
+// L_max never process their edges; so the lowered label's own entry (its
+// representative) is lowered too, and finalisation follows the pointers.
+__global__ void k_lp_round(const uint32_t* __restrict__ esrc, const uint32_t* __restrict__ edst,
+                           Ctrl* c, uint32_t* P, uint32_t slot) {
+  if (c->done) return;
+  const uint64_t E = c->edge_count;
+  bool any = false;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += wave_stride()) {
+    uint32_t u = esrc[e], v = edst[e];
+    uint32_t lu = ld(&P[u]), lv = ld(&P[v]);
+    if (lu == lv) continue;
+    if (lu < lv) {
+      uint32_t t = u;
+      u = v;
+      v = t;
+      t = lu;
+      lu = lv;
+      lv = t;
+    }
+    // now lu > lv: lower u and the representative lu
+    if (amin(&P[u], lv) > lv) any = true;
+    if (amin(&P[lu], lv) > lv) any = true;
+  }
+  if (any) mark_changed(c, slot);
+}
+
+// --------------------------------------------------------------- BFS sampling
+template <typename OffT>
+__global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) {
+  unsigned long long best = 0;
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    uint64_t v = base + lane();
+    unsigned long long key = 0;
+    if (v < n) {
+      uint64_t deg = (uint64_t)off[v + 1] - off[v];
+      if (deg > 0xFFFFFFFEull) deg = 0xFFFFFFFEull;
+      key = ((deg + 1) << 32) | (0xFFFFFFFFull - v);
+    }
+    best = key > best ? key : best;
+  }
+  // every lane of a wave ran the same iterations, so all are active here
+  best = wave_max(best);
+  if (lane() == 0 && best) atomicMax(&c->bfs_key, best);
+}
+
+template <typename OffT>
+__global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* visited,
+                            uint32_t* queue0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    uint32_t s = (uint32_t)(0xFFFFFFFFull - (c->bfs_key & 0xFFFFFFFFull));
+    c->bfs_source = s;
+    visited[s >> 5] |= 1u << (s & 31);
+    queue0[0] = s;
+    c->frontier_count[0] = 1;
+    c->frontier_count[1] = 0;
+    uint64_t deg = (uint64_t)off[s + 1] - off[s];
+    c->frontier_edges[0] = deg;
+    c->frontier_edges[1] = 0;
+    c->explored_edges = deg;
+  }
+}
+
+__global__ void k_bfs_level_reset(Ctrl* c, uint32_t nxt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->frontier_count[nxt] = 0;
+    c->frontier_edges[nxt] = 0;
+    c->small_count = 0;
+    c->seg_count = 0;
+  }
+}
+
+// Top-down: split the frontier queue into small vertices and segments.
+template <typename OffT>
+__global__ void k_bfs_td_split(const OffT* __restrict__ off, const uint32_t* __restrict__ queue,
+                               Ctrl* c, uint32_t cur, uint32_t* small, uint2* segs) {
+  const uint32_t count = c->frontier_count[cur];
+  for (uint64_t base = wave_base(); base < count; base += wave_stride()) {
+    uint64_t i = base + lane();
+    uint32_t u = 0;
+    uint64_t deg = 0;
+    if (i < count) {
+      u = queue[i];
+      deg = (uint64_t)off[u + 1] - off[u];
+    }
+    bool is_small = i < count && deg > 0 && deg <= kSmallDeg;
+    uint32_t nseg = (i < count && deg > kSmallDeg) ? (uint32_t)((deg + kSeg - 1) / kSeg) : 0;
+    uint32_t slot = wave_reserve(&c->small_count, is_small ? 1u : 0u);
+    if (is_small) small[slot] = u;
+    uint32_t sb = wave_reserve(&c->seg_count, nseg);
+    for (uint32_t t = 0; t < nseg; ++t) segs[sb + t] = make_uint2(u, t);
+  }
+}
+
+template <typename OffT>
+__device__ __forceinline__ void bfs_visit_td(const OffT* __restrict__ off, uint32_t u, uint32_t w,
+                                             uint32_t* visited, uint32_t* queue_out, Ctrl* c,
+                                             uint32_t nxt, uint32_t* fu, uint32_t* fv) {
+  uint32_t bit = 1u << (w & 31);
+  if (ld(&visited[w >> 5]) & bit) return;
+  uint32_t old = atomicOr(&visited[w >> 5], bit);
+  if (old & bit) return;
+  uint32_t pos = atomicAdd(&c->frontier_count[nxt], 1u);
+  queue_out[pos] = w;
+  uint64_t deg = (uint64_t)off[w + 1] - off[w];
+  atomicAdd(&c->frontier_edges[nxt], (unsigned long long)deg);
+  atomicAdd(&c->explored_edges, (unsigned long long)deg);
+  if (fu) {
+    fu[w] = u;
+    fv[w] = w;
+  }
+}
+
+template <typename OffT>
+__global__ void k_bfs_td_small(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                               const uint32_t* __restrict__ small, Ctrl* c, uint32_t nxt,
+                               uint32_t* visited, uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
+  const uint32_t count = c->small_count;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += wave_stride()) {
+    uint32_t u = small[i];
+    for (uint64_t x = off[u]; x < (uint64_t)off[u + 1]; ++x)
+      bfs_visit_td(off, u, nbrs[x], visited, queue_out, c, nxt, fu, fv);
+  }
+}
+
+template <typename OffT>
+__global__ void k_bfs_td_segs(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                              const uint2* __restrict__ segs, Ctrl* c, uint32_t nxt,
+                              uint32_t* visited, uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
+  const uint32_t count = c->seg_count;
+  for (uint64_t s = wave_index(); s < count; s += wave_count()) {
+    uint2 sg = segs[s];
+    uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
+    uint64_t e = off[sg.x + 1];
+    if (e > b + kSeg) e = b + kSeg;
+    for (uint64_t x = b + lane(); x < e; x += 64)
+      bfs_visit_td(off, sg.x, nbrs[x], visited, queue_out, c, nxt, fu, fv);
+  }
+}
+
+__global__ void k_queue_to_bits(const uint32_t* __restrict__ queue, const Ctrl* c, uint32_t cur,
+                                uint32_t* bits) {
+  const uint32_t count = c->frontier_count[cur];
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += wave_stride()) {
+    uint32_t w = queue[i];
+    atomicOr(&bits[w >> 5], 1u << (w & 31));
+  }
+}
+
+__global__ void k_bits_to_queue(const uint32_t* __restrict__ bits, uint32_t words, Ctrl* c,
+                                uint32_t slot_counter, uint32_t* queue) {
+  // counts are already known; rebuild the queue from the bitmap into slot order
+  for (uint64_t base = wave_base(); base < words; base += wave_stride()) {
+    uint64_t i = base + lane();
+    uint32_t word = i < words ? bits[i] : 0u;
+    uint32_t pos = wave_reserve(&c->small_count, (uint32_t)__popc(word));
+    while (word) {
+      uint32_t b = __ffs(word) - 1;
+      queue[pos++] = (uint32_t)(i * 32 + b);
+      word &= word - 1;
+    }
+  }
+  (void)slot_counter;
+}
+
+// Bottom-up: every unvisited vertex looks for a neighbour in the frontier.
+template <typename OffT>
+__global__ void k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                         uint32_t n, uint32_t* visited, const uint32_t* __restrict__ fr_in,
+                         uint32_t* fr_out, Ctrl* c, uint32_t nxt, uint32_t* fu, uint32_t* fv) {
+  uint32_t found = 0;
+  unsigned long long found_edges = 0;
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    uint64_t v = base + lane();
+    if (v < n && !(visited[v >> 5] & (1u << (v & 31)))) {
+      uint64_t b = off[v], e = off[v + 1];
+      for (uint64_t x = b; x < e; ++x) {
+        uint32_t w = nbrs[x];
+        if (fr_in[w >> 5] & (1u << (w & 31))) {
+          atomicOr(&visited[v >> 5], 1u << (v & 31));
+          atomicOr(&fr_out[v >> 5], 1u << (v & 31));
+          if (fu) {
+            fu[v] = w;
+            fv[v] = (uint32_t)v;
+          }
+          ++found;
+          found_edges += e - b;
+          break;
+        }
+      }
+    }
+  }
+  if (found) {
+    atomicAdd(&c->frontier_count[nxt], found);
+    atomicAdd(&c->frontier_edges[nxt], found_edges);
+    atomicAdd(&c->explored_edges, found_edges);
+  }
+}
+
+// Re-root the BFS component at its minimum id (the BFS labels reached vertices
+// with the source, which is not the component minimum).
+__global__ void k_bfs_min(const uint32_t* __restrict__ visited, uint32_t words, Ctrl* c) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += wave_stride()) {
+    uint32_t w = visited[i];
+    if (w) atomicMin(&c->comp_min, (uint32_t)(i * 32 + (__ffs(w) - 1)));
+  }
+}
+
+__global__ void k_bfs_label(const uint32_t* __restrict__ visited, uint32_t n, const Ctrl* c,
+                            uint32_t* P) {
+  const uint32_t r = c->comp_min;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride())
+    if (visited[v >> 5] & (1u << (v & 31))) P[v] = r;
+}
+
+// --------------------------------------------------------------- incremental
+template <class R>
+__global__ void k_query(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint64_t q,
+                        uint32_t* P, uint8_t* out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += wave_stride()) {
+    uint32_t ra = find<R::kFind>(P, a[i]);
+    uint32_t rb = find<R::kFind>(P, b[i]);
+    out[i] = (uint8_t)(ra == rb);
+  }
+}
+
+// =============================================================== host side
+namespace {
+
+constexpr uint32_t kPersistentBlocks = 2048;  // 256 CUs x 8 resident workgroups
+
+template <class Fn>
+gconn_status with_rule(int link, int find_rule, int splice, Fn&& fn) {
+  switch (link) {
+    case GCONN_LINK_ECL:
+      return fn(Rule<kUnionAsync, kFindHalve, 0>{});
+    case GCONN_LINK_ASYNC:
+      switch (find_rule) {
+        case kFindNaive: return fn(Rule<kUnionAsync, kFindNaive, 0>{});
+        case kFindSplit: return fn(Rule<kUnionAsync, kFindSplit, 0>{});
+        case kFindHalve: return fn(Rule<kUnionAsync, kFindHalve, 0>{});
+        default: return fn(Rule<kUnionAsync, kFindCompress, 0>{});
+      }
+    case GCONN_LINK_HOOKS:
+      switch (find_rule) {
+        case kFindNaive: return fn(Rule<kUnionHooks, kFindNaive, 0>{});
+        case kFindSplit: return fn(Rule<kUnionHooks, kFindSplit, 0>{});
+        case kFindHalve: return fn(Rule<kUnionHooks, kFindHalve, 0>{});
+        default: return fn(Rule<kUnionHooks, kFindCompress, 0>{});
+      }
+    case GCONN_LINK_EARLY:
+      switch (find_rule) {
+        case kFindNaive: return fn(Rule<kUnionEarly, kFindNaive, 0>{});
+        case kFindSplit: return fn(Rule<kUnionEarly, kFindSplit, 0>{});
+        case kFindHalve: return fn(Rule<kUnionEarly, kFindHalve, 0>{});
+        default: return fn(Rule<kUnionEarly, kFindCompress, 0>{});
+      }
+    case GCONN_LINK_REM_CAS:
+      if (splice == kSpliceSplitOne) {
+        switch (find_rule) {
+          case kFindNaive: return fn(Rule<kUnionRemCas, kFindNaive, kSpliceSplitOne>{});
+          case kFindSplit: return fn(Rule<kUnionRemCas, kFindSplit, kSpliceSplitOne>{});
+          default: return fn(Rule<kUnionRemCas, kFindHalve, kSpliceSplitOne>{});
+        }
+      } else {
+        switch (find_rule) {
+          case kFindNaive: return fn(Rule<kUnionRemCas, kFindNaive, kSpliceHalveOne>{});
+          case kFindSplit: return fn(Rule<kUnionRemCas, kFindSplit, kSpliceHalveOne>{});
+          default: return fn(Rule<kUnionRemCas, kFindHalve, kSpliceHalveOne>{});
+        }
+      }
+    default:
+      // SV / LT / LP: the sampling phase still runs union-find.
+      return fn(Rule<kUnionAsync, kFindSplit, 0>{});
+  }
+}
+
+struct Run {
+  const gconn_graph& g;
+  uint32_t* P;
+  uint32_t* fu;
+  uint32_t* fv;
+  uint8_t* ws;
+  const WsLayout& L;
+  const gconn_options& o;
+  bool want_stats;
+  hipStream_t s;
+  uint32_t block;
+  Ctrl* ctrl;
+  uint32_t* small;
+  uint2* segs;
+  uint32_t* hooks;
+  uint64_t rounds = 0;
+
+  Run(const gconn_graph& g_, uint32_t* P_, uint32_t* fu_, uint32_t* fv_, uint8_t* ws_,
+      const WsLayout& L_, const gconn_options& o_, bool st, hipStream_t s_)
+      : g(g_), P(P_), fu(fu_), fv(fv_), ws(ws_), L(L_), o(o_), want_stats(st), s(s_) {
+    block = (uint32_t)o.block;
+    ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+    small = reinterpret_cast<uint32_t*>(ws + L.small);
+    segs = reinterpret_cast<uint2*>(ws + L.segs);
+    hooks = (o.link == GCONN_LINK_HOOKS) ? reinterpret_cast<uint32_t*>(ws + L.hooks) : nullptr;
+  }
+
+  uint32_t gridN(uint64_t items) const { return grid_for(items, block); }
+
+  LinkCtx link_ctx() const {
+    LinkCtx c;
+    c.P = P;
+    c.H = hooks;
+    c.fu = fu;
+    c.fv = fv;
+    c.hooks = want_stats ? &ctrl->stat_hooks : nullptr;
+    return c;
+  }
+
+  gconn_status read_ctrl(Ctrl* host) {
+    GCONN_HIP(hipMemcpyAsync(host, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    GCONN_HIP(hipStreamSynchronize(s));
+    return GCONN_OK;
+  }
+
+  template <typename OffT>
+  gconn_status sample_phase() {
+    const OffT* off = static_cast<const OffT*>(g.offsets);
+    const uint32_t n = g.n;
+    Ctrl* st = want_stats ? ctrl : nullptr;
+    if (o.sample == GCONN_SAMPLE_KOUT) {
+      GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+        using R = decltype(rule);
+        k_sample_kout<R, OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, n, o.k, o.kout_random,
+                                                          o.seed ^ 0x6b6f7574ull, link_ctx(), st);
+        GCONN_LAUNCHED("k_sample_kout");
+        return GCONN_OK;
+      }));
+    } else if (o.sample == GCONN_SAMPLE_HB) {
+      k_hb_step1<OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, P, n, fu, fv, st);
+      GCONN_LAUNCHED("k_hb_step1");
+      GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+        using R = decltype(rule);
+        k_hb_step2<R, OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, n, o.hb_n, link_ctx(), st);
+        GCONN_LAUNCHED("k_hb_step2");
+        return GCONN_OK;
+      }));
+    } else if (o.sample == GCONN_SAMPLE_BFS) {
+      GCONN_TRY(bfs_phase<OffT>());
+    }
+    if (o.sample != GCONN_SAMPLE_BFS) {
+      k_compress<<<gridN(n), block, 0, s>>>(P, P, n);
+      GCONN_LAUNCHED("k_compress");
+    }
+    k_lmax<<<1, 1024, 0, s>>>(P, n, o.lmax_samples, o.seed, ctrl);
+    GCONN_LAUNCHED("k_lmax");
+    return GCONN_OK;
+  }
+
+  template <typename OffT>
+  gconn_status bfs_phase() {
+    const OffT* off = static_cast<const OffT*>(g.offsets);
+    const uint32_t n = g.n;
+    const uint32_t words = (n + 31) / 32;
+    uint32_t* visited = reinterpret_cast<uint32_t*>(ws + L.visited);
+    uint32_t* bits[2] = {reinterpret_cast<uint32_t*>(ws + L.fr_bits0),
+                         reinterpret_cast<uint32_t*>(ws + L.fr_bits1)};
+    uint32_t* queue[2] = {reinterpret_cast<uint32_t*>(ws + L.queue0),
+                          reinterpret_cast<uint32_t*>(ws + L.queue1)};
+    k_fill<<<gridN(words), block, 0, s>>>(visited, 0u, words);
+    GCONN_LAUNCHED("k_fill(visited)");
+    k_bfs_argmax<OffT><<<gridN(n), block, 0, s>>>(off, n, ctrl);
+    GCONN_LAUNCHED("k_bfs_argmax");
+    k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0]);
+    GCONN_LAUNCHED("k_bfs_start");
+    // Direction-optimising parameters (Beamer, Asanovic, Patterson, SC'12).
+    const double alpha = 14.0, beta = 24.0;
+    bool bottom_up = false;
+    bool have_queue = true;  // frontier `cur` is held as a queue (else as bits)
+    Ctrl h;
+    for (uint32_t level = 0;; ++level) {
+      const uint32_t cur = level & 1, nxt = cur ^ 1;
+      GCONN_TRY(read_ctrl(&h));
+      if (h.frontier_count[cur] == 0) break;
+      ++rounds;
+      const double m_f = (double)h.frontier_edges[cur];
+      const double m_u = (double)g.m - (double)h.explored_edges;
+      if (!bottom_up && m_f > m_u / alpha) bottom_up = true;
+      else if (bottom_up && (double)h.frontier_count[cur] < (double)n / beta) bottom_up = false;
+      k_bfs_level_reset<<<1, 64, 0, s>>>(ctrl, nxt);
+      GCONN_LAUNCHED("k_bfs_level_reset");
+      if (bottom_up) {
+        if (have_queue) {
+          k_fill<<<gridN(words), block, 0, s>>>(bits[cur], 0u, words);
+          GCONN_LAUNCHED("k_fill(bits)");
+          k_queue_to_bits<<<gridN(h.frontier_count[cur]), block, 0, s>>>(queue[cur], ctrl, cur,
+                                                                          bits[cur]);
+          GCONN_LAUNCHED("k_queue_to_bits");
+        }
+        k_fill<<<gridN(words), block, 0, s>>>(bits[nxt], 0u, words);
+        GCONN_LAUNCHED("k_fill(bits)");
+        k_bfs_bu<OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, n, visited, bits[cur], bits[nxt],
+                                                  ctrl, nxt, fu, fv);
+        GCONN_LAUNCHED("k_bfs_bu");
+        have_queue = false;
+      } else {
+        if (!have_queue) {
+          // rebuild the queue of `cur` from its bitmap (small_count is the cursor)
+          k_bits_to_queue<<<gridN(words), block, 0, s>>>(bits[cur], words, ctrl, cur, queue[cur]);
+          GCONN_LAUNCHED("k_bits_to_queue");
+          k_bfs_level_reset<<<1, 64, 0, s>>>(ctrl, nxt);
+          GCONN_LAUNCHED("k_bfs_level_reset");
+        }
+        k_bfs_td_split<OffT><<<gridN(h.frontier_count[cur]), block, 0, s>>>(off, queue[cur], ctrl,
+                                                                             cur, small, segs);
+        GCONN_LAUNCHED("k_bfs_td_split");
+        k_bfs_td_small<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, small, ctrl, nxt,
+                                                                 visited, queue[nxt], fu, fv);
+        GCONN_LAUNCHED("k_bfs_td_small");
+        k_bfs_td_segs<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, segs, ctrl, nxt,
+                                                                visited, queue[nxt], fu, fv);
+        GCONN_LAUNCHED("k_bfs_td_segs");
+        have_queue = true;
+      }
+    }
+    k_bfs_min<<<gridN(words), block, 0, s>>>(visited, words, ctrl);
+    GCONN_LAUNCHED("k_bfs_min");
+    k_bfs_label<<<gridN(n), block, 0, s>>>(visited, n, ctrl, P);
+    GCONN_LAUNCHED("k_bfs_label");
+    // the gather lists were used as scratch: reset their counters
+    k_bfs_level_reset<<<1, 64, 0, s>>>(ctrl, 0);
+    GCONN_LAUNCHED("k_bfs_level_reset");
+    return GCONN_OK;
+  }
+
+  template <typename OffT>
+  gconn_status gather() {
+    const OffT* off = static_cast<const OffT*>(g.offsets);
+    k_gather<OffT><<<gridN(g.n), block, 0, s>>>(off, P, g.n, ctrl, small, segs, want_stats ? 1 : 0);
+    GCONN_LAUNCHED("k_gather");
+    return GCONN_OK;
+  }
+
+  template <typename OffT>
+  gconn_status finish_union_find() {
+    const OffT* off = static_cast<const OffT*>(g.offsets);
+    return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+      using R = decltype(rule);
+      k_finish_small<R, OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, small, ctrl,
+                                                                  link_ctx());
+      GCONN_LAUNCHED("k_finish_small");
+      k_finish_segs<R, OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, segs, ctrl,
+                                                                 link_ctx());
+      GCONN_LAUNCHED("k_finish_segs");
+      return GCONN_OK;
+    });
+  }
+
+  template <typename OffT>
+  gconn_status materialize(uint32_t* esrc, uint32_t* edst) {
+    const OffT* off = static_cast<const OffT*>(g.offsets);
+    k_materialize_small<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, small, ctrl, esrc,
+                                                                  edst);
+    GCONN_LAUNCHED("k_materialize_small");
+    k_materialize_segs<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, segs, ctrl, esrc,
+                                                                 edst);
+    GCONN_LAUNCHED("k_materialize_segs");
+    return GCONN_OK;
+  }
+
+  // SV / LT / LP: K early-exit rounds per host check.
+  gconn_status iterate(uint32_t* esrc, uint32_t* edst) {
+    const uint32_t n = g.n;
+    uint32_t* prev = reinterpret_cast<uint32_t*>(ws + L.prev);
+    const bool sv = o.link == GCONN_LINK_SV, lt = o.link == GCONN_LINK_LT;
+    const int v = o.lt_variant;
+    // variant decoding, paper order: CUSA CRSA PUSA PRSA PUS PRS EUSA EUS, then F-forms
+    static const int kConnect[16] = {0, 0, 1, 1, 1, 1, 2, 2, 0, 0, 1, 1, 1, 1, 2, 2};
+    static const int kRoot[16] = {0, 1, 0, 1, 0, 1, 0, 0, 0, 1, 0, 1, 0, 1, 0, 0};
+    static const int kAlter[16] = {1, 1, 1, 1, 0, 0, 1, 0, 1, 1, 1, 1, 0, 0, 1, 0};
+    const bool full = v >= 8;
+    const bool need_prev = sv || (lt && kRoot[v]);
+    if (need_prev) {
+      k_copy<<<gridN(n), block, 0, s>>>(prev, P, n);
+      GCONN_LAUNCHED("k_copy(prev)");
+    }
+    const bool sv_snapshot = sv && fu != nullptr;
+    for (uint64_t r = 0;; r += kRoundsPerSync) {
+      for (int j = 0; j < kRoundsPerSync; ++j) {
+        const uint32_t rr = (uint32_t)(r + j);
+        const uint32_t slot = rr % kRoundSlots;
+        k_round_begin<<<1, 64, 0, s>>>(ctrl, rr);
+        GCONN_LAUNCHED("k_round_begin");
+        if (sv) {
+          k_sv_round<<<kPersistentBlocks, block, 0, s>>>(esrc, edst, ctrl, P, prev, slot,
+                                                         sv_snapshot ? 1 : 0);
+          GCONN_LAUNCHED("k_sv_round");
+          if (fu) {
+            k_sv_record<<<kPersistentBlocks, block, 0, s>>>(esrc, edst, ctrl, P, prev, fu, fv);
+            GCONN_LAUNCHED("k_sv_record");
+          }
+          k_shortcut_full<<<gridN(n), block, 0, s>>>(ctrl, P, prev, n, slot, 0);
+          GCONN_LAUNCHED("k_shortcut_full");
+        } else if (lt) {
+          k_lt_round<<<kPersistentBlocks, block, 0, s>>>(esrc, edst, ctrl, P, prev, slot,
+                                                         kConnect[v], kRoot[v]);
+          GCONN_LAUNCHED("k_lt_round");
+          if (full) {
+            k_shortcut_full<<<gridN(n), block, 0, s>>>(ctrl, P, kRoot[v] ? prev : nullptr, n,
+                                                       slot, 1);
+            GCONN_LAUNCHED("k_shortcut_full");
+          } else {
+            k_shortcut_one<<<gridN(n), block, 0, s>>>(ctrl, P, kRoot[v] ? prev : nullptr, n, slot);
+            GCONN_LAUNCHED("k_shortcut_one");
+          }
+          if (kAlter[v]) {
+            k_lt_alter<<<kPersistentBlocks, block, 0, s>>>(esrc, edst, ctrl, P, slot);
+            GCONN_LAUNCHED("k_lt_alter");
+          }
+        } else {
+          k_lp_round<<<kPersistentBlocks, block, 0, s>>>(esrc, edst, ctrl, P, slot);
+          GCONN_LAUNCHED("k_lp_round");
+        }
+      }
+      uint32_t done = 0;
+      GCONN_HIP(hipMemcpyAsync(&done, &ctrl->done, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      GCONN_HIP(hipStreamSynchronize(s));
+      if (done) {
+        // count the rounds that ran: find the first slot that reported no change
+        Ctrl h;
+        GCONN_TRY(read_ctrl(&h));
+        uint64_t ran = r + kRoundsPerSync;
+        for (int j = 0; j < kRoundsPerSync; ++j)
+          if (h.changed[(r + j) % kRoundSlots] == 0) {
+            ran = r + j + 1;
+            break;
+          }
+        rounds = ran;
+        break;
+      }
+      if (r + kRoundsPerSync >= kMaxRounds)
+        return fail(GCONN_ETIMEOUT, "iterative finish did not converge within the round cap");
+    }
+    return GCONN_OK;
+  }
+};
+
+}  // namespace
+
+gconn_status launch_iota(uint32_t* P, uint32_t n, hipStream_t s) {
+  if (n == 0) return GCONN_OK;
+  k_iota<<<grid_for(n, 256), 256, 0, s>>>(P, n);
+  GCONN_LAUNCHED("k_iota");
+  return GCONN_OK;
+}
+
+gconn_status launch_fill(uint32_t* p, uint32_t value, uint64_t count, hipStream_t s) {
+  if (count == 0) return GCONN_OK;
+  k_fill<<<grid_for(count, 256), 256, 0, s>>>(p, value, count);
+  GCONN_LAUNCHED("k_fill");
+  return GCONN_OK;
+}
+
+gconn_status launch_finalize(uint32_t* P, uint32_t n, uint32_t* labels, hipStream_t s) {
+  if (n == 0) return GCONN_OK;
+  k_compress<<<grid_for(n, 256), 256, 0, s>>>(P, labels, n);
+  GCONN_LAUNCHED("k_compress(finalize)");
+  return GCONN_OK;
+}
+
+gconn_status launch_insert(const gconn_options& o, uint32_t* P, uint32_t* H, const uint32_t* src,
+                           const uint32_t* dst, uint64_t k, hipStream_t s) {
+  if (k == 0) return GCONN_OK;
+  LinkCtx c;
+  c.P = P;
+  c.H = H;
+  c.fu = c.fv = nullptr;
+  c.hooks = nullptr;
+  const uint32_t block = (uint32_t)o.block;
+  return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+    using R = decltype(rule);
+    k_unite_pairs<R><<<grid_for(k, block), block, 0, s>>>(src, dst, k, c);
+    GCONN_LAUNCHED("k_unite_pairs");
+    return GCONN_OK;
+  });
+}
+
+gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a,
+                          const uint32_t* b, uint64_t q, uint8_t* out, hipStream_t s) {
+  if (q == 0) return GCONN_OK;
+  const uint32_t block = (uint32_t)o.block;
+  return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+    using R = decltype(rule);
+    k_query<R><<<grid_for(q, block), block, 0, s>>>(a, b, q, P, out);
+    GCONN_LAUNCHED("k_query");
+    return GCONN_OK;
+  });
+}
+
+gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, uint32_t n,
+                            Ctrl* ctrl, hipStream_t s) {
+  if (k == 0) return GCONN_OK;
+  k_ctrl_init<<<1, 256, 0, s>>>(ctrl);
+  GCONN_LAUNCHED("k_ctrl_init");
+  k_validate_ids<<<grid_for(k, 256), 256, 0, s>>>(a, b, k, n, ctrl);
+  GCONN_LAUNCHED("k_validate_ids");
+  uint32_t err = 0;
+  GCONN_HIP(hipMemcpyAsync(&err, &ctrl->err, sizeof(err), hipMemcpyDeviceToHost, s));
+  GCONN_HIP(hipStreamSynchronize(s));
+  if (err) return fail(GCONN_EINVAL, "vertex id out of range in batch");
+  return GCONN_OK;
+}
+
+WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool forest, bool labels) {
+  WsLayout L;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t p = at;
+    at = align_up(at + (bytes ? bytes : 1), 256);
+    return p;
+  };
+  const uint64_t n = g.n, m = g.m;
+  L.ctrl = take(sizeof(Ctrl));
+  if (forest && !labels) L.P = take(4 * n);
+  const bool csr = g.format == GCONN_CSR;
+  if (csr) {
+    L.small = take(4 * n);
+    L.seg_cap = m / (kSmallDeg + 1) + 1;
+    L.segs = take(8 * L.seg_cap);
+  }
+  if (o.link == GCONN_LINK_HOOKS) L.hooks = take(4 * n);
+  const bool iterative =
+      o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
+  if (iterative) {
+    L.prev = take(4 * n);
+    L.edge_cap = m;
+    L.esrc = take(4 * m);
+    L.edst = take(4 * m);
+  }
+  if (csr && o.sample == GCONN_SAMPLE_BFS) {
+    const uint64_t words = (n + 31) / 32;
+    L.visited = take(4 * words);
+    L.fr_bits0 = take(4 * words);
+    L.fr_bits1 = take(4 * words);
+    L.queue0 = take(4 * n);
+    L.queue1 = take(4 * n);
+  }
+  L.total = at;
+  return L;
+}
+
+gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_t* fv,
+                        bool finalize, uint8_t* ws, const WsLayout& L, const gconn_options& o,
+                        gconn_stats* stats, hipStream_t s) {
+  Run run(g, P, fu, fv, ws, L, o, stats != nullptr, s);
+  const uint32_t n = g.n;
+  const uint32_t block = run.block;
+  k_ctrl_init<<<1, 256, 0, s>>>(run.ctrl);
+  GCONN_LAUNCHED("k_ctrl_init");
+  if (n > 0) {
+    k_init<<<grid_for(n, block), block, 0, s>>>(P, n, fu, fv);
+    GCONN_LAUNCHED("k_init");
+  }
+  if (run.hooks) GCONN_TRY(launch_fill(run.hooks, kEmpty, n, s));
+
+  const bool csr = g.format == GCONN_CSR;
+  const bool o64 = g.offsets_64 != 0;
+  if (o.validate && (g.m > 0 || csr)) {
+    if (csr) {
+      if (o64)
+        k_validate_csr<uint64_t><<<grid_for(std::max<uint64_t>(g.m, n), block), block, 0, s>>>(
+            static_cast<const uint64_t*>(g.offsets), g.nbrs, n, g.m, run.ctrl);
+      else
+        k_validate_csr<uint32_t><<<grid_for(std::max<uint64_t>(g.m, n), block), block, 0, s>>>(
+            static_cast<const uint32_t*>(g.offsets), g.nbrs, n, g.m, run.ctrl);
+    } else {
+      k_validate_ids<<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m, n, run.ctrl);
+    }
+    GCONN_LAUNCHED("k_validate");
+    uint32_t err = 0;
+    GCONN_HIP(hipMemcpyAsync(&err, &run.ctrl->err, sizeof(err), hipMemcpyDeviceToHost, s));
+    GCONN_HIP(hipStreamSynchronize(s));
+    if (err) return fail(GCONN_EINVAL, "graph validation failed (offsets or vertex id out of range)");
+  }
+
+  const bool iterative =
+      o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
+  if (n > 0 && g.m > 0) {
+    if (csr) {
+      if (o.sample != GCONN_SAMPLE_NONE)
+        GCONN_TRY(o64 ? run.sample_phase<uint64_t>() : run.sample_phase<uint32_t>());
+      GCONN_TRY(o64 ? run.gather<uint64_t>() : run.gather<uint32_t>());
+    }
+    if (!iterative) {
+      if (csr) {
+        GCONN_TRY(o64 ? run.finish_union_find<uint64_t>() : run.finish_union_find<uint32_t>());
+      } else {
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          k_unite_pairs<R><<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m,
+                                                                  run.link_ctx());
+          GCONN_LAUNCHED("k_unite_pairs");
+          return GCONN_OK;
+        }));
+      }
+    } else {
+      uint32_t* esrc = reinterpret_cast<uint32_t*>(ws + L.esrc);
+      uint32_t* edst = reinterpret_cast<uint32_t*>(ws + L.edst);
+      if (csr) {
+        GCONN_TRY(o64 ? run.materialize<uint64_t>(esrc, edst) : run.materialize<uint32_t>(esrc, edst));
+      } else {
+        k_materialize_coo<<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m, run.ctrl, esrc,
+                                                                edst);
+        GCONN_LAUNCHED("k_materialize_coo");
+      }
+      GCONN_TRY(run.iterate(esrc, edst));
+    }
+    if (finalize || o.link == GCONN_LINK_ECL) {
+      // ECL-CC's separate full-compress pass doubles as finalisation.
+      k_compress<<<grid_for(n, block), block, 0, s>>>(P, P, n);
+      GCONN_LAUNCHED("k_compress(finalize)");
+    }
+  }
+  if (stats) {
+    Ctrl h;
+    GCONN_TRY(run.read_ctrl(&h));
+    stats->sampled_edges = h.stat_sampled;
+    stats->active_vertices = h.stat_active;
+    stats->finish_edges = h.stat_finish_edges;
+    stats->hooks = h.stat_hooks;
+    stats->rounds = run.rounds;
+    stats->lmax = h.lmax;
+    stats->bfs_source = h.bfs_source;
+  }
+  return GCONN_OK;
+}
+
+}  // namespace gconn

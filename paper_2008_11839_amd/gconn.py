@@ -1,0 +1,317 @@
+"""ctypes binding of libgconn.so (the C ABI in include/gconn.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  Vertex-id tensors are int32 tensors holding uint32 bit patterns
+(0xFFFFFFFF, the empty forest slot, reads as -1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgconn.so")
+EMPTY = 0xFFFFFFFF
+
+SAMPLE = {"none": 0, "kout": 1, "hb": 2, "bfs": 3}
+LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt": 6, "lp": 7}
+FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3}
+SPLICE = {"split_one": 0, "halve_one": 1}
+LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
+               "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]
+STATUS = {0: "GCONN_OK", -1: "GCONN_EINVAL", -2: "GCONN_ENOMEM", -3: "GCONN_EDEVICE",
+          -4: "GCONN_ENODEV", -5: "GCONN_EBUSY", -6: "GCONN_ETIMEOUT", -7: "GCONN_EUNSUPPORTED"}
+
+
+class GconnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_int32), ("offsets_64", ctypes.c_int32),
+                ("n", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("m", ctypes.c_uint64), ("offsets", ctypes.c_void_p),
+                ("nbrs", ctypes.c_void_p), ("dst", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("sample", ctypes.c_int32), ("link", ctypes.c_int32), ("find", ctypes.c_int32),
+                ("splice", ctypes.c_int32), ("lt_variant", ctypes.c_int32),
+                ("k", ctypes.c_uint32), ("hb_n", ctypes.c_uint32),
+                ("lmax_samples", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("kout_random", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("sampled_edges", ctypes.c_uint64), ("active_vertices", ctypes.c_uint64),
+                ("finish_edges", ctypes.c_uint64), ("hooks", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint64), ("lmax", ctypes.c_uint32),
+                ("bfs_source", ctypes.c_uint32)]
+
+
+EXPORTS = ["gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
+           "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
+           "gconn_inc_query_batch", "gconn_inc_labels", "gconn_inc_destroy",
+           "gconn_status_string", "gconn_last_error", "gconn_version"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgconn.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2008_11839_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        gp, op, stp = ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Stats)
+        L.gconn_options_default.restype = None
+        L.gconn_options_default.argtypes = [op]
+        L.gconn_workspace_size.restype = ctypes.c_int
+        L.gconn_workspace_size.argtypes = [gp, op, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)]
+        L.gconn_cc.restype = ctypes.c_int
+        L.gconn_cc.argtypes = [gp, vp, vp, sz, op, stp, vp]
+        L.gconn_spanning_forest.restype = ctypes.c_int
+        L.gconn_spanning_forest.argtypes = [gp, vp, vp, vp, vp, sz, op, stp, vp]
+        L.gconn_inc_workspace_size.restype = ctypes.c_int
+        L.gconn_inc_workspace_size.argtypes = [ctypes.c_uint32, gp, op, ctypes.POINTER(sz)]
+        L.gconn_inc_create.restype = ctypes.c_int
+        L.gconn_inc_create.argtypes = [ctypes.c_uint32, vp, gp, vp, sz, op, vp,
+                                       ctypes.POINTER(vp)]
+        L.gconn_inc_insert_batch.restype = ctypes.c_int
+        L.gconn_inc_insert_batch.argtypes = [vp, vp, vp, ctypes.c_uint64, vp]
+        L.gconn_inc_query_batch.restype = ctypes.c_int
+        L.gconn_inc_query_batch.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp]
+        L.gconn_inc_labels.restype = ctypes.c_int
+        L.gconn_inc_labels.argtypes = [vp, vp, vp]
+        L.gconn_inc_destroy.restype = ctypes.c_int
+        L.gconn_inc_destroy.argtypes = [vp]
+        L.gconn_status_string.restype = ctypes.c_char_p
+        L.gconn_status_string.argtypes = [ctypes.c_int]
+        L.gconn_last_error.restype = ctypes.c_char_p
+        L.gconn_last_error.argtypes = []
+        L.gconn_version.restype = ctypes.c_char_p
+        L.gconn_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        msg = lib().gconn_last_error().decode(errors="replace")
+        raise GconnError(status, msg)
+
+
+@dataclass
+class Options:
+    """Python view of gconn_options (names instead of enum values)."""
+    sample: str = "kout"
+    link: str = "async"
+    find: str = "split"
+    splice: str = "split_one"
+    lt_variant: str = "PRF"
+    k: int = 2
+    hb_n: int = 4
+    lmax_samples: int = 1024
+    seed: int = 1
+    kout_random: bool = False
+    validate: bool = False
+    block: int = 256
+
+    def to_c(self) -> _Options:
+        o = _Options()
+        lib().gconn_options_default(ctypes.byref(o))
+        o.sample = SAMPLE[self.sample]
+        o.link = LINK[self.link]
+        o.find = FIND[self.find]
+        o.splice = SPLICE[self.splice]
+        o.lt_variant = LT_VARIANTS.index(self.lt_variant)
+        o.k, o.hb_n, o.lmax_samples = self.k, self.hb_n, self.lmax_samples
+        o.seed = self.seed
+        o.kout_random = int(self.kout_random)
+        o.validate = int(self.validate)
+        o.block = self.block
+        return o
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+@dataclass
+class DeviceGraph:
+    """A graph resident in device memory (CSR or COO) plus its C descriptor."""
+    n: int
+    m: int
+    fmt: str
+    offsets: torch.Tensor | None = None
+    nbrs: torch.Tensor | None = None
+    dst: torch.Tensor | None = None
+    c: _Graph = field(default_factory=_Graph)
+
+    def __post_init__(self):
+        g = self.c
+        g.format = 0 if self.fmt == "csr" else 1
+        g.n = self.n
+        g.m = self.m
+        g.offsets_64 = int(self.offsets is not None and self.offsets.dtype == torch.int64)
+        g.offsets = _ptr(self.offsets) if self.offsets is not None else None
+        g.nbrs = _ptr(self.nbrs) if self.nbrs is not None and self.nbrs.numel() else None
+        g.dst = _ptr(self.dst) if self.dst is not None and self.dst.numel() else None
+
+
+def csr(offsets, nbrs, n: int | None = None, device="cuda", offsets64: bool | None = None) -> DeviceGraph:
+    """Upload (or wrap) a CSR graph.  offsets: n+1 entries; nbrs: m ids."""
+    if isinstance(offsets, np.ndarray):
+        m = int(offsets[-1]) if len(offsets) else 0
+        if offsets64 is None:
+            offsets64 = m > 0xFFFFFFFF
+        off = torch.from_numpy(offsets.astype(np.int64 if offsets64 else np.uint32).view(
+            np.int64 if offsets64 else np.int32)).to(device)
+    else:
+        off = offsets
+    if isinstance(nbrs, np.ndarray):
+        nb = torch.from_numpy(np.ascontiguousarray(nbrs, dtype=np.uint32).view(np.int32)).to(device)
+    else:
+        nb = nbrs
+    n = off.numel() - 1 if n is None else n
+    return DeviceGraph(n=n, m=nb.numel(), fmt="csr", offsets=off, nbrs=nb)
+
+
+def coo(src, dst, n: int, device="cuda") -> DeviceGraph:
+    conv = lambda a: (torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)
+                      if isinstance(a, np.ndarray) else a)
+    s, d = conv(src), conv(dst)
+    return DeviceGraph(n=n, m=s.numel(), fmt="coo", nbrs=s, dst=d)
+
+
+def workspace_size(g: DeviceGraph, options: Options | None = None, forest: bool = False,
+                   labels: bool = True) -> int:
+    o = (options or Options()).to_c()
+    b = ctypes.c_size_t(0)
+    _check(lib().gconn_workspace_size(ctypes.byref(g.c), ctypes.byref(o), int(forest), int(labels),
+                                      ctypes.byref(b)))
+    return b.value
+
+
+def alloc_workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    """Device buffer of at least nbytes whose data_ptr is 256-byte aligned."""
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + nbytes]
+
+
+def _stats_dict(s: _Stats) -> dict:
+    return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+
+def cc(g: DeviceGraph, labels: torch.Tensor | None = None, options: Options | None = None,
+       workspace: torch.Tensor | None = None, stats: bool = False, stream=None):
+    """Connected-component labels (minimum vertex id per component), int32 tensor."""
+    o = (options or Options()).to_c()
+    if labels is None:
+        labels = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.nbrs.device if g.nbrs is not None else "cuda")[: g.n]
+    if workspace is None:
+        workspace = alloc_workspace(workspace_size(g, options))
+    st = _Stats() if stats else None
+    _check(lib().gconn_cc(ctypes.byref(g.c), _ptr(labels) if g.n else None, workspace.data_ptr(),
+                          workspace.numel(), ctypes.byref(o), ctypes.byref(st) if st else None,
+                          _stream(stream)))
+    return (labels, _stats_dict(st)) if stats else labels
+
+
+def spanning_forest(g: DeviceGraph, want_labels: bool = True, options: Options | None = None,
+                    workspace: torch.Tensor | None = None, stats: bool = False, stream=None):
+    """Per-slot forest edges (fu, fv) (-1 = empty slot) and optional labels."""
+    o = (options or Options()).to_c()
+    dev = g.nbrs.device if g.nbrs is not None else torch.device("cuda")
+    fu = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)[: g.n]
+    fv = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)[: g.n]
+    labels = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)[: g.n] if want_labels else None
+    if workspace is None:
+        workspace = alloc_workspace(workspace_size(g, options, forest=True, labels=want_labels))
+    st = _Stats() if stats else None
+    _check(lib().gconn_spanning_forest(ctypes.byref(g.c), _ptr(fu) if g.n else None,
+                                       _ptr(fv) if g.n else None,
+                                       _ptr(labels) if (labels is not None and g.n) else None,
+                                       workspace.data_ptr(), workspace.numel(), ctypes.byref(o),
+                                       ctypes.byref(st) if st else None, _stream(stream)))
+    out = (fu, fv, labels)
+    return (*out, _stats_dict(st)) if stats else out
+
+
+class Incremental:
+    """Handle over gconn_inc_*: batched edge insertion and connectivity queries."""
+
+    def __init__(self, n_max: int, initial: DeviceGraph | None = None,
+                 options: Options | None = None, device="cuda", stream=None):
+        self.options = options or Options(sample="none")
+        o = self.options.to_c()
+        self.n_max = n_max
+        self.parent = torch.empty(max(n_max, 1), dtype=torch.int32, device=device)
+        b = ctypes.c_size_t(0)
+        gp = ctypes.byref(initial.c) if initial is not None else None
+        _check(lib().gconn_inc_workspace_size(n_max, gp, ctypes.byref(o), ctypes.byref(b)))
+        self.workspace = alloc_workspace(b.value, device)
+        self._initial = initial  # keep device buffers alive while the handle is
+        h = ctypes.c_void_p()
+        _check(lib().gconn_inc_create(n_max, self.parent.data_ptr(), gp, self.workspace.data_ptr(),
+                                      self.workspace.numel(), ctypes.byref(o), _stream(stream),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def insert(self, src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+        _check(lib().gconn_inc_insert_batch(self._h, _ptr(src), _ptr(dst), src.numel(),
+                                            _stream(stream)))
+
+    def query(self, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(a.numel(), 1), dtype=torch.uint8, device=a.device)[: a.numel()]
+        _check(lib().gconn_inc_query_batch(self._h, _ptr(a), _ptr(b), a.numel(),
+                                           _ptr(out) if a.numel() else None, _stream(stream)))
+        return out
+
+    def labels(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(max(self.n_max, 1), dtype=torch.int32, device=self.parent.device)[: self.n_max]
+        _check(lib().gconn_inc_labels(self._h, _ptr(out) if self.n_max else None, _stream(stream)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().gconn_inc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_u32(t: torch.Tensor) -> np.ndarray:
+    """Device int32 tensor -> host uint32 array (bit pattern preserved)."""
+    return t.detach().cpu().numpy().view(np.uint32)

@@ -1,0 +1,80 @@
+"""Write tests/golden/<config>.json from the CPU oracle alone.
+
+Each record pins, for one seeded full-size workload: its size, the number of
+components, the largest component, a SHA-256 of the canonical labels (uint32
+little-endian), and the sampling-phase intermediates (L_max over the default
+seeded sample of 1024 vertices with seed 1, active vertices and active edges)
+for k-out (k = 2) and hook-based (N = 4) sampling.  Only `graphgen` (inputs)
+and `oracle` are used.
+
+    python tests/golden/make_golden.py [config ...]
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+
+CONFIGS = {
+    "er_n100000_m1000000_s1": lambda: graphgen.er(100_000, 1_000_000, 1),
+    "rmat24_ef16_s1": lambda: graphgen.rmat(24, 16, 1),
+    "grid2d_4096_p07_s1": lambda: graphgen.grid2d(4096, 4096, 0.7, 1),
+    "grid3d_256_p06_s1": lambda: graphgen.grid3d(256, 256, 256, 0.6, 1),
+}
+LMAX_SAMPLES, LMAX_SEED = 1024, 1
+
+
+def sha(labels: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(labels, dtype="<u4").tobytes()).hexdigest()
+
+
+def record(name: str) -> dict:
+    t0 = time.time()
+    G = CONFIGS[name]()
+    t1 = time.time()
+    lab = oracle.cc(G.n, G.offsets, G.nbrs)
+    t2 = time.time()
+    roots = lab == np.arange(G.n, dtype=np.uint32)
+    sizes = np.bincount(lab.astype(np.int64), minlength=G.n)
+    rec = {
+        "config": name, "n": G.n, "m": G.m,
+        "components": int(roots.sum()), "largest_component": int(sizes.max()),
+        "labels_sha256": sha(lab),
+        "isolated": int((G.degrees() == 0).sum()),
+        "oracle_cc_seconds": round(t2 - t1, 2), "generate_seconds": round(t1 - t0, 2),
+    }
+    for sampler in ("kout", "hb"):
+        if sampler == "kout":
+            s_lab, e = oracle.sample_kout(G.n, G.offsets, G.nbrs, 2)
+        else:
+            s_lab, e = oracle.sample_hb(G.n, G.offsets, G.nbrs, 4)
+        L = oracle.lmax(s_lab, LMAX_SAMPLES, LMAX_SEED)
+        rec[sampler] = {"sampled_edges": e, "lmax": L,
+                        "active_vertices": oracle.active_count(G.n, G.offsets, s_lab, L),
+                        "active_edges": oracle.active_edges(G.n, G.offsets, s_lab, L),
+                        "sampled_labels_sha256": sha(s_lab)}
+    return rec
+
+
+def main(names):
+    out_dir = os.path.dirname(os.path.abspath(__file__))
+    for name in names:
+        rec = record(name)
+        with open(os.path.join(out_dir, name + ".json"), "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+        print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(CONFIGS))
