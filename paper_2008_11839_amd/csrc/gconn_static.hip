@@ -281,8 +281,8 @@ __global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, ui
 // when there was no sampling, so every vertex with edges is active).
 template <typename OffT>
 __global__ void k_gather(const OffT* __restrict__ off, const uint32_t* __restrict__ P, uint32_t n,
-                         Ctrl* c, uint32_t* small, uint2* segs, int want_stats) {
-  const uint32_t lmax = c->lmax;
+                         Ctrl* c, uint32_t* small, uint2* segs, int want_stats, int skip_lmax) {
+  const uint32_t lmax = skip_lmax ? c->lmax : kEmpty;
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
     uint64_t v = base + lane();
     uint64_t deg = 0;
@@ -554,30 +554,40 @@ __global__ void k_lt_alter(uint32_t* esrc, uint32_t* edst, Ctrl* c, const uint32
 }
 
 // Label propagation round: across an edge with different labels the larger
-// label is lowered to the smaller.  After sampling, labels are compressed
-// pointers shared by a whole sampled component, and the vertices labelled
-// L_max never process their edges; so the lowered label's own entry (its
-// representative) is lowered too, and finalisation follows the pointers.
+// label is lowered to the smaller.  After sampling, the vertices labelled L_max
+// never process their edges, so the edges inside that group are never seen
+// and its members must move together: every vertex whose entry holds L_max is
+// treated as one node whose current label lives at P[L_max] (lowering it
+// lowers the whole group, which finalisation then follows).  Without sampling
+// L_max is the empty sentinel and this is plain label propagation.
+__device__ __forceinline__ void lp_label(const uint32_t* P, uint32_t x, uint32_t group,
+                                         uint32_t* label, uint32_t* slot) {
+  uint32_t l = ld(&P[x]);
+  uint32_t t = x;
+  if (l == group) {
+    t = group;
+    l = ld(&P[group]);
+  }
+  *label = l;
+  *slot = t;
+}
+
 __global__ void k_lp_round(const uint32_t* __restrict__ esrc, const uint32_t* __restrict__ edst,
                            Ctrl* c, uint32_t* P, uint32_t slot) {
   if (c->done) return;
   const uint64_t E = c->edge_count;
+  const uint32_t group = c->lmax;
   bool any = false;
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += wave_stride()) {
-    uint32_t u = esrc[e], v = edst[e];
-    uint32_t lu = ld(&P[u]), lv = ld(&P[v]);
+    uint32_t lu, tu, lv, tv;
+    lp_label(P, esrc[e], group, &lu, &tu);
+    lp_label(P, edst[e], group, &lv, &tv);
     if (lu == lv) continue;
-    if (lu < lv) {
-      uint32_t t = u;
-      u = v;
-      v = t;
-      t = lu;
-      lu = lv;
-      lv = t;
+    if (lu > lv) {
+      if (amin(&P[tu], lv) > lv) any = true;
+    } else {
+      if (amin(&P[tv], lu) > lu) any = true;
     }
-    // now lu > lv: lower u and the representative lu
-    if (amin(&P[u], lv) > lv) any = true;
-    if (amin(&P[lu], lv) > lv) any = true;
   }
   if (any) mark_changed(c, slot);
 }
@@ -864,6 +874,21 @@ struct Run {
 
   uint32_t gridN(uint64_t items) const { return grid_for(items, block); }
 
+  // Liu-Tarjan variants whose connect rule sends labels to the edge endpoints
+  // under Update (CUSA, CUFA, EUSA, EUS, EUFA, EUF) may re-point a vertex of
+  // the L_max group away from its group, whose internal edges the finish never
+  // sees; they process every vertex instead of skipping the L_max group.
+  bool skip_lmax() const {
+    if (o.link != GCONN_LINK_LT) return true;
+    switch (o.lt_variant) {
+      case GCONN_LT_CUSA: case GCONN_LT_CUFA: case GCONN_LT_EUSA: case GCONN_LT_EUS:
+      case GCONN_LT_EUFA: case GCONN_LT_EUF:
+        return false;
+      default:
+        return true;
+    }
+  }
+
   LinkCtx link_ctx() const {
     LinkCtx c;
     c.P = P;
@@ -993,7 +1018,8 @@ struct Run {
   template <typename OffT>
   gconn_status gather() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
-    k_gather<OffT><<<gridN(g.n), block, 0, s>>>(off, P, g.n, ctrl, small, segs, want_stats ? 1 : 0);
+    k_gather<OffT><<<gridN(g.n), block, 0, s>>>(off, P, g.n, ctrl, small, segs, want_stats ? 1 : 0,
+                                                skip_lmax() ? 1 : 0);
     GCONN_LAUNCHED("k_gather");
     return GCONN_OK;
   }
@@ -1086,8 +1112,10 @@ struct Run {
         // count the rounds that ran: find the first slot that reported no change
         Ctrl h;
         GCONN_TRY(read_ctrl(&h));
+        // the first round (from the last one of the previous batch on) that
+        // reported no change is the converged round; count it
         uint64_t ran = r + kRoundsPerSync;
-        for (int j = 0; j < kRoundsPerSync; ++j)
+        for (int64_t j = (r > 0 ? -1 : 0); j < kRoundsPerSync; ++j)
           if (h.changed[(r + j) % kRoundSlots] == 0) {
             ran = r + j + 1;
             break;
