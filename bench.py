@@ -1,0 +1,310 @@
+#!/usr/bin/env python3
+"""Benchmark: static connectivity on RMAT-24 on one MI355X.
+
+Workload (default): RMAT scale 24, edge factor 16, quadrant probabilities
+(0.57, 0.19, 0.19, 0.05), seeded id scramble, symmetrised CSR with sorted rows
+(n = 2^24, m = 536,865,446 directed entries), seed 1.  Method: k-out sampling
+(first k = 2 edges) + Union-Rem-CAS with SplitAtomicOne splicing and
+AtomicSplit compression, then finalisation -- one gconn_cc call per step, the
+graph already resident in HBM, parent-array initialisation included.
+
+Prints ONE JSON line on stdout: throughput in Gedges/s (directed CSR entries
+per second), the roofline of the dominant kernel (algorithmic bytes over its
+HIP-event-timed duration, against 8 TB/s), the CPU oracle timed on the host,
+per-phase times, the spanning-forest throughput and an incremental
+(insert/query batch) measurement on the same graph's edge stream.
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "static CC Gedges/s on RMAT-24 (% HBM roofline); incremental updates/s + p99"
+KERNEL_SOURCES = ["paper_2008_11839_amd/csrc/gconn_static.hip",
+                  "paper_2008_11839_amd/csrc/gconn_rules.hpp"]
+# phase -> kernel launched in it (single-kernel phases)
+PHASE_KERNEL = {"init_ms": "k_init", "sample_ms": "k_sample_kout", "compress_ms": "k_compress",
+                "lmax_ms": "k_lmax", "gather_ms": "k_gather", "finish_ms": "k_finish_small+segs",
+                "finalize_ms": "k_compress(finalize)"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
+    """Bytes each phase must move at 4-byte granularity (uint32 ids and labels).
+
+    init: write P (4n).  sample (k-out): read offsets (4(n+1)) and, per sampled
+    entry, the neighbour id plus the two parent entries the union reads (12 B).
+    compress: read + write P (8n).  lmax: one label per sample.  gather: read
+    offsets and P (8n), write the active list (4A).  finish: offsets of the
+    active vertices (8A) and 12 B per finish entry.  finalize: read + write P.
+    """
+    Es, A, Ef = st["sampled_edges"], st["active_vertices"], st["finish_edges"]
+    return {"init_ms": 4 * n, "sample_ms": 4 * (n + 1) + 12 * Es, "compress_ms": 8 * n,
+            "lmax_ms": 4 * samples, "gather_ms": 8 * n + 4 * A, "finish_ms": 8 * A + 12 * Ef,
+            "finalize_ms": 8 * n}
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * p / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--scale", type=int, default=24, help="RMAT scale (24 = the benchmark workload)")
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--sample", default="kout")
+    ap.add_argument("--link", default="rem_cas")
+    ap.add_argument("--find", default="split")
+    ap.add_argument("--splice", default="split_one")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the spanning-forest and incremental measurements")
+    ap.add_argument("--inc-batch", type=int, default=1_000_000)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the method runs on "
+              "a single MI355X; multi-GPU sharding is a design note, not part of this build.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    from paper_2008_11839_amd import gconn as G
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    props = torch.cuda.get_device_properties(0)
+    log(f"device {props.name} gcn={getattr(props, 'gcnArchName', '?')} "
+        f"CUs={props.multi_processor_count}")
+
+    # ------------------------------------------------------------ workload
+    t0 = time.time()
+    n = 1 << args.scale
+    src, dst = graphgen.rmat_edges(args.scale, args.edge_factor * n, args.seed)
+    C = graphgen.csr_from_edges(n, src, dst, True, f"rmat{args.scale}_ef{args.edge_factor}_s{args.seed}")
+    m = C.m
+    log(f"generated {C.name}: n={n} m={m} in {time.time() - t0:.1f}s")
+    dg = G.csr(C.offsets, C.nbrs, n)  # uint32 offsets (m < 2^32)
+    torch.cuda.synchronize()
+    opts = G.Options(sample=args.sample, link=args.link, find=args.find, splice=args.splice,
+                     block=args.block)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = G.alloc_workspace(G.workspace_size(dg, opts))
+    stream = torch.cuda.current_stream()
+
+    # ------------------------------------------------------------ stats + parity (untimed)
+    lab, st = G.cc(dg, labels=labels, options=opts, workspace=ws, stats=True)
+    torch.cuda.synchronize()
+    got = G.to_u32(lab)
+    got_sha = hashlib.sha256(np.ascontiguousarray(got, dtype="<u4").tobytes()).hexdigest()
+    golden_path = os.path.join(ROOT, "tests", "golden", f"{C.name}.json")
+    parity = None
+    if os.path.exists(golden_path):
+        with open(golden_path) as f:
+            parity = json.load(f)["labels_sha256"] == got_sha
+    log(f"stats {st} parity_vs_oracle_golden={parity}")
+
+    # ------------------------------------------------------------ timed region
+    for _ in range(args.warmup):
+        G.cc(dg, labels=labels, options=opts, workspace=ws)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        G.cc(dg, labels=labels, options=opts, workspace=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_per_step = wall * 1e3 / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    value = m / (ms_per_step * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step wall, {ev_ms:.4f} ms/step events, "
+        f"{value:.1f} Gedges/s")
+
+    # ------------------------------------------------------------ per-phase HIP events
+    G.profile_enable(True)
+    G.profile_read(reset=True)
+    for _ in range(args.steps):
+        G.cc(dg, labels=labels, options=opts, workspace=ws)
+    torch.cuda.synchronize()
+    ph = G.profile_read(reset=True)
+    G.profile_enable(False)
+    runs = max(ph.pop("runs"), 1)
+    phase_ms = {k: v / runs for k, v in ph.items()}
+    abytes = algorithmic_bytes(n, m, st, opts.lmax_samples)
+    dominant = max((k for k in phase_ms if k != "finish_ms"), key=lambda k: phase_ms[k])
+    dom_ms = phase_ms[dominant]
+    achieved = abytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+    total_alg = sum(abytes.values())
+    log(f"phases (ms): {json.dumps({k: round(v, 4) for k, v in phase_ms.items()})}")
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_rmat24.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            rec = json.load(f)
+        if rec.get("source_sha") == source_sha() and rec.get("kernel") == PHASE_KERNEL[dominant]:
+            traffic = rec.get("hbm_bytes_per_launch")
+
+    roofline = {
+        "bound": "hbm", "kernel": PHASE_KERNEL[dominant],
+        "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": traffic,
+        "alg_bytes_per_launch": abytes[dominant], "launch_ms": round(dom_ms, 5),
+        "step_alg_bytes": total_alg,
+        "step_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gedges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"RMAT-{args.scale} ef{args.edge_factor} (0.57,0.19,0.19,0.05) "
+                               f"scrambled ids, symmetrised CSR, seed {args.seed}",
+                   "n": n, "m_directed": m, "sample": args.sample, "link": args.link,
+                   "find": args.find, "splice": args.splice, "block": args.block,
+                   "parity_vs_oracle": parity},
+        "roofline": roofline,
+        "phases_ms": {k: round(v, 5) for k, v in phase_ms.items()},
+        "event_ms_per_step": round(ev_ms, 5),
+        "stats": st,
+    }
+
+    # ------------------------------------------------------------ spanning forest
+    if not args.no_extras:
+        fu = torch.empty(n, dtype=torch.int32, device=dev)
+        fv = torch.empty(n, dtype=torch.int32, device=dev)
+        ws_f = G.alloc_workspace(G.workspace_size(dg, opts, forest=True, labels=False))
+        lib = G.lib()
+        o = opts.to_c()
+        import ctypes
+
+        def sf_step():
+            G._check(lib.gconn_spanning_forest(ctypes.byref(dg.c), fu.data_ptr(), fv.data_ptr(),
+                                               None, ws_f.data_ptr(), ws_f.numel(), ctypes.byref(o),
+                                               None, stream.cuda_stream))
+        for _ in range(args.warmup):
+            sf_step()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(args.steps):
+            sf_step()
+        torch.cuda.synchronize()
+        sf_ms = (time.perf_counter() - w0) * 1e3 / args.steps
+        filled = int((fu != -1).sum().item())
+        comps = int((torch.from_numpy(got.view(np.int32)).to(dev) ==
+                     torch.arange(n, dtype=torch.int32, device=dev)).sum().item())
+        result["spanning_forest"] = {"ms_per_step": round(sf_ms, 5),
+                                     "gedges_per_s": round(m / (sf_ms * 1e-3) / 1e9, 2),
+                                     "forest_edges": filled, "n_minus_c": n - comps}
+        log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")
+        del fu, fv, ws_f
+
+        # -------------------------------------------------------- incremental batches
+        # the generated edge list holds each undirected edge once, in random order
+        s_in = torch.from_numpy(src.view(np.int32)).to(dev)
+        d_in = torch.from_numpy(dst.view(np.int32)).to(dev)
+        qa, qb = graphgen.uniform_pairs(n, 100_000, args.seed, 0)
+        qa_t = torch.from_numpy(qa.view(np.int32)).to(dev)
+        qb_t = torch.from_numpy(qb.view(np.int32)).to(dev)
+        qout = torch.empty(len(qa), dtype=torch.uint8, device=dev)
+        k_total = s_in.numel()
+        B = args.inc_batch
+        inc_opts = G.Options(sample="none", link="async", find="split")
+        inc = G.Incremental(n, options=inc_opts)
+        torch.cuda.synchronize()
+        lat_ins, lat_q = [], []
+        evs = []
+        w0 = time.perf_counter()
+        for b0 in range(0, k_total, B):
+            e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e_a.record(stream)
+            inc.insert(s_in[b0:b0 + B], d_in[b0:b0 + B])
+            e_b.record(stream)
+            q_a, q_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            q_a.record(stream)
+            inc.query(qa_t, qb_t, out=qout)
+            q_b.record(stream)
+            evs.append((e_a, e_b, q_a, q_b))
+        torch.cuda.synchronize()
+        inc_wall = time.perf_counter() - w0
+        for e_a, e_b, q_a, q_b in evs:
+            lat_ins.append(e_a.elapsed_time(e_b))
+            lat_q.append(q_a.elapsed_time(q_b))
+        ins_ms = sum(lat_ins)
+        inc_labels = G.to_u32(inc.labels())
+        inc.close()
+        result["incremental"] = {
+            "workload": f"{C.name} undirected edges streamed once in generation order, "
+                        f"insert batches of {B} interleaved with 1e5-pair query batches, "
+                        "device-resident, Union-Async + FindSplit",
+            "updates": k_total, "insert_updates_per_s": round(k_total / (ins_ms * 1e-3), 1),
+            "insert_batch_ms_p50": round(percentile(lat_ins, 50), 4),
+            "insert_batch_ms_p99": round(percentile(lat_ins, 99), 4),
+            "query_batch_ms_p50": round(percentile(lat_q, 50), 4),
+            "query_batch_ms_p99": round(percentile(lat_q, 99), 4),
+            "wall_updates_per_s": round(k_total / inc_wall, 1),
+            "labels_match_static": bool(np.array_equal(inc_labels, got)),
+        }
+        log(f"incremental {result['incremental']}")
+        del s_in, d_in
+
+    # ------------------------------------------------------------ CPU oracle baseline
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        want = oracle.cc(n, C.offsets, C.nbrs)
+        t_cpu = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": round(m / t_cpu / 1e9, 4), "unit": "Gedges/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full {C.name} graph, one run of the sequential union-find oracle "
+                      f"({t_cpu:.1f} s, generation excluded)",
+            "seconds": round(t_cpu, 2),
+            "labels_match_gpu": bool(np.array_equal(want, got)),
+        }
+        log(f"cpu oracle {t_cpu:.2f}s match={result['cpu_baseline']['labels_match_gpu']}")
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

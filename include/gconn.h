@@ -195,6 +195,26 @@ gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream);
 /* Frees the host handle only (no device memory is owned). */
 gconn_status gconn_inc_destroy(gconn_inc* h);
 
+/* Per-phase device time of the static pipeline (gconn_cc, gconn_spanning_forest,
+ * the initial graph of gconn_inc_create).  While profiling is enabled on the
+ * calling thread, each phase is bracketed by HIP events recorded on the call's
+ * own stream; gconn_profile_read waits for those events and adds up the
+ * elapsed times (milliseconds).  Disabled by default. */
+typedef struct gconn_phase_times {
+  double init_ms;      /* control block, parent array, forest slots, hooks   */
+  double sample_ms;    /* sampling kernels (k-out, hook-based, BFS levels)    */
+  double compress_ms;  /* full compression after sampling                     */
+  double lmax_ms;      /* most frequent label                                 */
+  double gather_ms;    /* vertex gathering (active lists)                     */
+  double finish_ms;    /* finish phase, every round included                  */
+  double finalize_ms;  /* label finalisation (or ECL-CC's compress pass)      */
+  uint64_t runs;       /* pipeline runs accumulated                           */
+} gconn_phase_times;
+
+gconn_status gconn_profile_enable(int on);
+/* Fills *out with the totals since the last reset; reset = 1 clears them. */
+gconn_status gconn_profile_read(gconn_phase_times* out, int reset);
+
 const char* gconn_status_string(gconn_status s);
 /* Message for the most recent failure on the calling thread ("" if none). */
 const char* gconn_last_error(void);

@@ -315,6 +315,13 @@ gconn_status gconn_inc_destroy(gconn_inc* h) {
   return GCONN_OK;
 }
 
+gconn_status gconn_profile_enable(int on) { return profile_enable(on); }
+
+gconn_status gconn_profile_read(gconn_phase_times* out, int reset) {
+  clear_error();
+  return profile_read(out, reset);
+}
+
 const char* gconn_status_string(gconn_status s) {
   switch (s) {
     case GCONN_OK: return "GCONN_OK";

@@ -113,6 +113,17 @@ gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, ui
 gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a,
                           const uint32_t* b, uint64_t q, uint8_t* out, hipStream_t s);
 
+// Phase profiler (thread-local; HIP events on the caller's stream).
+enum Phase : int {
+  kPhaseInit = 0, kPhaseSample, kPhaseCompress, kPhaseLmax, kPhaseGather, kPhaseFinish,
+  kPhaseFinalize, kPhaseCount
+};
+bool profiling();
+gconn_status prof_mark(int phase, bool begin, hipStream_t s);
+void prof_count_run();
+gconn_status profile_enable(int on);
+gconn_status profile_read(gconn_phase_times* out, int reset);
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 inline uint32_t grid_for(uint64_t items, uint32_t block, uint32_t cap = 1u << 20) {

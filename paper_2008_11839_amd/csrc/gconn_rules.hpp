@@ -6,13 +6,17 @@
 // with a smaller ID).  All rules are root-based: a CAS only ever turns a root
 // into a child, always of a smaller id, so no cycle can form.
 //
-// Memory model.  The eight XCDs of an MI355X each have a private L2, so a plain
-// load inside a retry loop could keep returning a stale line.  Every read of P
-// inside a find / union loop is therefore a relaxed agent-scope atomic load
-// (global_load ... sc1), and every write is an agent-scope atomic (CAS, min,
-// store).  Correctness never depends on a read being fresh: any value P[x] has
-// ever held is an ancestor of x in the current forest, and each CAS
-// re-validates; the coherent loads only guarantee progress.
+// Memory model.  The eight XCDs of an MI355X each have a private L2 that is
+// not kept coherent with the others inside a kernel.  Every write to P is an
+// agent-scope atomic (CAS, min, store).  Reads of P inside find / union loops
+// are relaxed atomic loads whose scope is GCONN_P_LOAD_SCOPE; at workgroup
+// scope they are ordinary cached loads (L2 hits for the hot entries near the
+// roots of large trees) and may return stale values.  Correctness never
+// depends on a read being fresh: any value P[x] has ever held is an ancestor
+// of x in the current forest, and every link is a CAS that re-validates.
+// Progress does not depend on it either: every loop iteration below either
+// moves to a strictly smaller id, or continues from the value a failed CAS
+// returned (which is fresh), so no loop can spin on a stale line.
 //
 // Readings of the appendix pseudocode (Appendix A.2, find / splice / union
 // algorithms) where it is garbled:
@@ -37,7 +41,16 @@ enum FindRule : int { kFindNaive = 0, kFindSplit = 1, kFindHalve = 2, kFindCompr
 enum SpliceRule : int { kSpliceSplitOne = 0, kSpliceHalveOne = 1 };
 enum UnionRule : int { kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnionRemCas = 3 };
 
+#ifndef GCONN_P_LOAD_SCOPE
+#define GCONN_P_LOAD_SCOPE __HIP_MEMORY_SCOPE_AGENT
+#endif
+
+// Read of P inside a find / union loop (see the memory-model note above).
 __device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, GCONN_P_LOAD_SCOPE);
+}
+// Device-coherent read (flags and counters polled across XCDs).
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
@@ -85,19 +98,21 @@ __device__ __forceinline__ uint32_t find(uint32_t* P, uint32_t u) {
   } else if constexpr (F == kFindSplit) {
     for (;;) {
       uint32_t v = ld(&P[u]);
+      if (v == u) return u;
       uint32_t w = ld(&P[v]);
       if (v == w) return v;
       uint32_t e = v;
       cas(&P[u], e, w);
-      u = v;
+      u = v;  // v < u
     }
   } else if constexpr (F == kFindHalve) {
     for (;;) {
       uint32_t v = ld(&P[u]);
+      if (v == u) return u;
       uint32_t w = ld(&P[v]);
       if (v == w) return v;
       uint32_t e = v;
-      u = cas(&P[u], e, w) ? w : e;  // follow the new P[u]
+      u = cas(&P[u], e, w) ? w : e;  // the new P[u], smaller than u either way
     }
   } else {  // kFindCompress
     uint32_t r = u;
@@ -233,7 +248,7 @@ __device__ __forceinline__ bool union_rem_cas(const LinkCtx& c, uint32_t u, uint
         }
         return true;
       }
-      continue;
+      pru = e;  // ru was linked meanwhile: continue from its fresh parent
     }
     uint32_t w = ld(&c.P[pru]);
     if (w != pru) {

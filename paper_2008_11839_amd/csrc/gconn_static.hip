@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "gconn_internal.hpp"
 #include "gconn_rules.hpp"
@@ -910,6 +911,7 @@ struct Run {
     const OffT* off = static_cast<const OffT*>(g.offsets);
     const uint32_t n = g.n;
     Ctrl* st = want_stats ? ctrl : nullptr;
+    GCONN_TRY(prof_mark(kPhaseSample, true, s));
     if (o.sample == GCONN_SAMPLE_KOUT) {
       GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
         using R = decltype(rule);
@@ -930,12 +932,17 @@ struct Run {
     } else if (o.sample == GCONN_SAMPLE_BFS) {
       GCONN_TRY(bfs_phase<OffT>());
     }
+    GCONN_TRY(prof_mark(kPhaseSample, false, s));
     if (o.sample != GCONN_SAMPLE_BFS) {
+      GCONN_TRY(prof_mark(kPhaseCompress, true, s));
       k_compress<<<gridN(n), block, 0, s>>>(P, P, n);
       GCONN_LAUNCHED("k_compress");
+      GCONN_TRY(prof_mark(kPhaseCompress, false, s));
     }
+    GCONN_TRY(prof_mark(kPhaseLmax, true, s));
     k_lmax<<<1, 1024, 0, s>>>(P, n, o.lmax_samples, o.seed, ctrl);
     GCONN_LAUNCHED("k_lmax");
+    GCONN_TRY(prof_mark(kPhaseLmax, false, s));
     return GCONN_OK;
   }
 
@@ -1182,6 +1189,90 @@ gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a
   });
 }
 
+// --------------------------------------------------------------- phase profiler
+namespace {
+struct Profiler {
+  bool on = false;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open[kPhaseCount] = {};
+  double acc[kPhaseCount] = {};
+  uint64_t runs = 0;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+};
+thread_local Profiler g_prof;
+}  // namespace
+
+bool profiling() { return g_prof.on; }
+
+gconn_status prof_mark(int phase, bool begin, hipStream_t s) {
+  if (!g_prof.on) return GCONN_OK;
+  hipEvent_t e = g_prof.get();
+  if (!e) return fail(GCONN_EDEVICE, "hipEventCreate failed");
+  GCONN_HIP(hipEventRecord(e, s));
+  if (begin) {
+    g_prof.open[phase] = e;
+  } else {
+    g_prof.pending.push_back({phase, g_prof.open[phase], e});
+    g_prof.open[phase] = nullptr;
+  }
+  return GCONN_OK;
+}
+
+void prof_count_run() {
+  if (g_prof.on) ++g_prof.runs;
+}
+
+gconn_status profile_enable(int on) {
+  g_prof.on = on != 0;
+  return GCONN_OK;
+}
+
+gconn_status profile_read(gconn_phase_times* out, int reset) {
+  for (auto& m : g_prof.pending) {
+    GCONN_HIP(hipEventSynchronize(m.b));
+    float ms = 0.f;
+    if (m.a) {
+      GCONN_HIP(hipEventElapsedTime(&ms, m.a, m.b));
+      g_prof.pool.push_back(m.a);
+    }
+    g_prof.acc[m.phase] += ms;
+    g_prof.pool.push_back(m.b);
+  }
+  g_prof.pending.clear();
+  if (out) {
+    out->init_ms = g_prof.acc[kPhaseInit];
+    out->sample_ms = g_prof.acc[kPhaseSample];
+    out->compress_ms = g_prof.acc[kPhaseCompress];
+    out->lmax_ms = g_prof.acc[kPhaseLmax];
+    out->gather_ms = g_prof.acc[kPhaseGather];
+    out->finish_ms = g_prof.acc[kPhaseFinish];
+    out->finalize_ms = g_prof.acc[kPhaseFinalize];
+    out->runs = g_prof.runs;
+  }
+  if (reset) {
+    for (double& a : g_prof.acc) a = 0;
+    g_prof.runs = 0;
+  }
+  return GCONN_OK;
+}
+
 gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, uint32_t n,
                             Ctrl* ctrl, hipStream_t s) {
   if (k == 0) return GCONN_OK;
@@ -1240,6 +1331,8 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
   Run run(g, P, fu, fv, ws, L, o, stats != nullptr, s);
   const uint32_t n = g.n;
   const uint32_t block = run.block;
+  prof_count_run();
+  GCONN_TRY(prof_mark(kPhaseInit, true, s));
   k_ctrl_init<<<1, 256, 0, s>>>(run.ctrl);
   GCONN_LAUNCHED("k_ctrl_init");
   if (n > 0) {
@@ -1247,6 +1340,7 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
     GCONN_LAUNCHED("k_init");
   }
   if (run.hooks) GCONN_TRY(launch_fill(run.hooks, kEmpty, n, s));
+  GCONN_TRY(prof_mark(kPhaseInit, false, s));
 
   const bool csr = g.format == GCONN_CSR;
   const bool o64 = g.offsets_64 != 0;
@@ -1274,8 +1368,11 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
     if (csr) {
       if (o.sample != GCONN_SAMPLE_NONE)
         GCONN_TRY(o64 ? run.sample_phase<uint64_t>() : run.sample_phase<uint32_t>());
+      GCONN_TRY(prof_mark(kPhaseGather, true, s));
       GCONN_TRY(o64 ? run.gather<uint64_t>() : run.gather<uint32_t>());
+      GCONN_TRY(prof_mark(kPhaseGather, false, s));
     }
+    GCONN_TRY(prof_mark(kPhaseFinish, true, s));
     if (!iterative) {
       if (csr) {
         GCONN_TRY(o64 ? run.finish_union_find<uint64_t>() : run.finish_union_find<uint32_t>());
@@ -1300,10 +1397,13 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
       }
       GCONN_TRY(run.iterate(esrc, edst));
     }
+    GCONN_TRY(prof_mark(kPhaseFinish, false, s));
     if (finalize || o.link == GCONN_LINK_ECL) {
       // ECL-CC's separate full-compress pass doubles as finalisation.
+      GCONN_TRY(prof_mark(kPhaseFinalize, true, s));
       k_compress<<<grid_for(n, block), block, 0, s>>>(P, P, n);
       GCONN_LAUNCHED("k_compress(finalize)");
+      GCONN_TRY(prof_mark(kPhaseFinalize, false, s));
     }
   }
   if (stats) {

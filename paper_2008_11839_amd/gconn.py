@@ -57,7 +57,14 @@ class _Stats(ctypes.Structure):
                 ("bfs_source", ctypes.c_uint32)]
 
 
-EXPORTS = ["gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
+class _PhaseTimes(ctypes.Structure):
+    _fields_ = [("init_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
+                ("compress_ms", ctypes.c_double), ("lmax_ms", ctypes.c_double),
+                ("gather_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
+                ("finalize_ms", ctypes.c_double), ("runs", ctypes.c_uint64)]
+
+
+EXPORTS = ["gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
            "gconn_inc_query_batch", "gconn_inc_labels", "gconn_inc_destroy",
            "gconn_status_string", "gconn_last_error", "gconn_version"]
@@ -96,6 +103,10 @@ def lib() -> ctypes.CDLL:
         L.gconn_inc_labels.argtypes = [vp, vp, vp]
         L.gconn_inc_destroy.restype = ctypes.c_int
         L.gconn_inc_destroy.argtypes = [vp]
+        L.gconn_profile_enable.restype = ctypes.c_int
+        L.gconn_profile_enable.argtypes = [ctypes.c_int]
+        L.gconn_profile_read.restype = ctypes.c_int
+        L.gconn_profile_read.argtypes = [ctypes.POINTER(_PhaseTimes), ctypes.c_int]
         L.gconn_status_string.restype = ctypes.c_char_p
         L.gconn_status_string.argtypes = [ctypes.c_int]
         L.gconn_last_error.restype = ctypes.c_char_p
@@ -310,6 +321,17 @@ class Incremental:
             self.close()
         except Exception:
             pass
+
+
+def profile_enable(on: bool = True) -> None:
+    """Per-phase HIP-event timing of the pipeline on this thread (see gconn.h)."""
+    _check(lib().gconn_profile_enable(int(on)))
+
+
+def profile_read(reset: bool = True) -> dict:
+    t = _PhaseTimes()
+    _check(lib().gconn_profile_read(ctypes.byref(t), int(reset)))
+    return {f: getattr(t, f) for f, _ in _PhaseTimes._fields_}
 
 
 def to_u32(t: torch.Tensor) -> np.ndarray:
