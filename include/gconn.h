@@ -125,7 +125,10 @@ typedef struct gconn_options {
   int32_t kout_random;   /* 0: first k edges; 1: first edge + k-1 uniform picks  */
   int32_t validate;      /* 1: check the graph on the device first (synchronous) */
   int32_t block;         /* threads per workgroup, multiple of 64, <= 1024 (256) */
-  int32_t reserved;
+  int32_t schedule;      /* k-out kernel shape: 0 persistent lanes with the next
+                            vertex's row prefetched (default), 1 one lane per
+                            vertex, 2 lane-refill step machine (Union-Rem-CAS,
+                            first-k, uint32 offsets; else as 0)            (0) */
 } gconn_options;
 
 /* Counters filled when a stats pointer is passed (the call then synchronises

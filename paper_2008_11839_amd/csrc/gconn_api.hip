@@ -50,6 +50,7 @@ gconn_status check_options(const gconn_options& o) {
   if (o.hb_n < 1 || o.hb_n > 1024) return fail(GCONN_EINVAL, "options.hb_n must be in [1, 1024]");
   if (o.lmax_samples < 1 || o.lmax_samples > kMaxLmaxSamples)
     return fail(GCONN_EINVAL, "options.lmax_samples must be in [1, 4096]");
+  if (o.schedule < 0 || o.schedule > 2) return fail(GCONN_EINVAL, "options.schedule out of range");
   if (o.block < 64 || o.block > 1024 || (o.block % 64) != 0)
     return fail(GCONN_EINVAL, "options.block must be a multiple of 64 in [64, 1024]");
   return GCONN_OK;
@@ -157,6 +158,7 @@ void gconn_options_default(gconn_options* o) {
   o->kout_random = 0;
   o->validate = 0;
   o->block = 256;
+  o->schedule = 0;
 }
 
 gconn_status gconn_workspace_size(const gconn_graph* g, const gconn_options* opt, int want_forest,

@@ -11,10 +11,17 @@
 
 namespace gconn {
 
-// Small-vertex threshold: vertices with at most this many edges are processed
-// by one lane; larger ones are cut into segments of kSeg edges, one wave each.
+// Work classes of the finish phase (and of top-down BFS levels): a vertex
+// with at most kSmallDeg edges is handled by one lane, one with at most
+// kMedDeg edges by one wave64, and larger ones are cut into kSeg-edge
+// segments, one wave each.  Small and medium vertices are appended to
+// kSubLists sub-lists (chosen by the 64-vertex group of the appending wave) so
+// that the append counters are spread over many addresses: on this chip
+// atomics to a single address serialise at ~11 ns each.
 constexpr uint32_t kSmallDeg = 32;
+constexpr uint32_t kMedDeg = 1024;
 constexpr uint32_t kSeg = 1024;
+constexpr uint32_t kSubLists = 64;
 constexpr uint32_t kMaxLmaxSamples = 4096;
 constexpr int kRoundsPerSync = 8;        // device-side early-exit rounds per host check
 constexpr uint32_t kRoundSlots = 64;     // ring of per-round "changed" flags
@@ -24,13 +31,13 @@ constexpr uint64_t kMaxRounds = 1u << 24;
 // kernel, never by hipMemsetAsync, so a captured graph replays correctly).
 struct Ctrl {
   uint32_t lmax;
-  uint32_t small_count;
   uint32_t seg_count;
   uint32_t done;
   uint32_t err;
   uint32_t bfs_source;
   uint32_t comp_min;
   uint32_t frontier_count[2];
+  uint32_t queue_cursor;              // BFS bitmap -> queue rebuild
   uint32_t pad0;
   unsigned long long edge_count;      // materialised finish edges (SV/LT/LP)
   unsigned long long bfs_key;         // argmax-degree key
@@ -40,14 +47,17 @@ struct Ctrl {
   unsigned long long stat_active;
   unsigned long long stat_finish_edges;
   unsigned long long stat_hooks;
+  uint32_t small_cnt[kSubLists];
+  uint32_t medium_cnt[kSubLists];
   uint32_t changed[kRoundSlots];
 };
 
 struct WsLayout {
   size_t ctrl = 0;
   size_t P = 0;       // parent array when the caller gives no labels buffer
-  size_t small = 0;   // active small-vertex list (uint32[n])
-  size_t segs = 0;    // heavy-vertex segments (uint2[seg_cap])
+  size_t small = 0;   // small-vertex sub-lists (uint32[kSubLists][sub_cap])
+  size_t medium = 0;  // medium-vertex sub-lists (uint32[kSubLists][sub_cap])
+  size_t segs = 0;    // hub segments (uint2[seg_cap])
   size_t hooks = 0;   // Union-Hooks claim array (uint32[n])
   size_t prev = 0;    // round-start parents (SV, LT)
   size_t esrc = 0;    // materialised edges (SV, LT, LP)
@@ -55,6 +65,7 @@ struct WsLayout {
   size_t visited = 0; // BFS bitmap
   size_t fr_bits0 = 0, fr_bits1 = 0;  // BFS frontier bitmaps
   size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
+  uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;
   size_t total = 0;

@@ -41,8 +41,10 @@ enum FindRule : int { kFindNaive = 0, kFindSplit = 1, kFindHalve = 2, kFindCompr
 enum SpliceRule : int { kSpliceSplitOne = 0, kSpliceHalveOne = 1 };
 enum UnionRule : int { kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnionRemCas = 3 };
 
+// Wavefront scope compiles to an ordinary cached global load (measured fastest
+// for the union-find kernels on MI355X; see the memory-model note above).
 #ifndef GCONN_P_LOAD_SCOPE
-#define GCONN_P_LOAD_SCOPE __HIP_MEMORY_SCOPE_AGENT
+#define GCONN_P_LOAD_SCOPE __HIP_MEMORY_SCOPE_WAVEFRONT
 #endif
 
 // Read of P inside a find / union loop (see the memory-model note above).
@@ -168,7 +170,9 @@ __device__ __forceinline__ bool union_hooks(const LinkCtx& c, uint32_t u, uint32
       pu = pv;
       pv = t;
     }
-    uint32_t next = ld(&c.P[pu]);
+    // A stale "still a root" read here would send the lane to a hook CAS that
+    // is bound to fail, so this test reads the parent coherently.
+    uint32_t next = ld_agent(&c.P[pu]);
     if (next == pu) {
       uint32_t h = kEmpty;
       if (cas(&c.H[pu], h, pv)) {

@@ -5,15 +5,22 @@
 // Execution shape.  Streaming passes over the n vertices use one lane per
 // vertex in wave-uniform grid-stride loops (every lane of a wave runs the same
 // number of iterations, so wave-wide ballots, scans and shuffles are safe).
-// The finish phase first gathers the active vertices (label != L_max, degree
-// > 0; vertex gathering) into a small-vertex list, processed one lane per
-// vertex with its edges walked serially (the edge-reorganisation goal of no
-// same-vertex CAS conflicts inside a wave), and a heavy-vertex segment list,
-// one wave per segment of up to kSeg edges (load balancing of hubs).
+// Vertex gathering (the active set: label != L_max, degree > 0) fills three
+// work classes: one lane per small vertex with its edges walked serially (the
+// edge-reorganisation goal: no same-vertex CAS conflicts inside a wave), one
+// wave per medium vertex, one wave per 1024-edge segment of a hub.
+//
+// The k-out sampler for Union-Rem-CAS runs as a lane-refill step machine:
+// each lane owns a contiguous range of vertices and, every iteration, does one
+// step of its current union (one round of at most two loads, then at most one
+// CAS), moving on to its next edge or vertex as soon as a union ends.  Lanes
+// of a wave therefore never wait for each other's union chains, and every
+// iteration issues all lanes' loads together.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gconn_internal.hpp"
@@ -24,17 +31,18 @@ namespace gconn {
 // --------------------------------------------------------------- helpers
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 
-// Wave-uniform iteration: returns the first vertex handled by this wave.
+// Wave-uniform iteration: returns the first item handled by this wave.
 __device__ __forceinline__ uint64_t wave_base() {
   return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ull;
 }
-__device__ __forceinline__ uint64_t wave_stride() { return (uint64_t)gridDim.x * blockDim.x; }
-__device__ __forceinline__ uint64_t wave_index() {
-  return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+__device__ __forceinline__ uint64_t gtid() {
+  return (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
+__device__ __forceinline__ uint64_t wave_stride() { return (uint64_t)gridDim.x * blockDim.x; }
+__device__ __forceinline__ uint64_t wave_index() { return gtid() >> 6; }
 __device__ __forceinline__ uint64_t wave_count() { return ((uint64_t)gridDim.x * blockDim.x) >> 6; }
 
-// All 64 lanes must be active.
+// All 64 lanes must be active for the wave-wide helpers below.
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
   return x;
@@ -65,6 +73,17 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* counter, uint32_t cnt
   base = __shfl(base, 0);
   return base + off;
 }
+// One slot per lane with pred set; one atomic per wave (lanes may be inactive).
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred, bool* any) {
+  const unsigned long long mask = __ballot(pred);
+  *any = mask != 0;
+  if (!mask) return 0;
+  const uint32_t leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + (uint32_t)__popcll(mask & ((1ull << lane()) - 1));
+}
 
 __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state0, uint64_t i) {
   uint64_t z = state0 + (i + 1) * 0x9e3779b97f4a7c15ull;
@@ -73,6 +92,8 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t state0, uint64_t i) {
   return z ^ (z >> 31);
 }
 
+// Root by pointer jumping with plain loads: used only after a kernel boundary,
+// with no concurrent links, where every value read is an ancestor.
 __device__ __forceinline__ uint32_t root_plain(const uint32_t* P, uint32_t x) {
   uint32_t p = P[x];
   while (p != x) {
@@ -82,7 +103,90 @@ __device__ __forceinline__ uint32_t root_plain(const uint32_t* P, uint32_t x) {
   return x;
 }
 
+// --------------------------------------------------------------- work lists
+struct WorkLists {
+  uint32_t* small;   // [kSubLists][cap]
+  uint32_t* medium;  // [kSubLists][cap]
+  uint2* segs;       // (vertex, segment index)
+  uint32_t cap;
+};
+
+// Append vertex v (degree deg) to its work class.  `group` is the index of the
+// 64-item group this wave iteration covers (uniform over the wave); it picks
+// the sub-list, so one sub-list receives at most `cap` entries.  All 64 lanes
+// must be active.
+__device__ __forceinline__ void wl_push(const WorkLists& wl, Ctrl* c, uint64_t group, uint32_t v,
+                                        uint64_t deg, bool active) {
+  const uint32_t r = (uint32_t)(group % kSubLists);
+  const bool sm = active && deg <= kSmallDeg;
+  const bool md = active && deg > kSmallDeg && deg <= kMedDeg;
+  const bool lg = active && deg > kMedDeg;
+  bool any;
+  uint32_t slot = wave_append(&c->small_cnt[r], sm, &any);
+  if (sm) wl.small[(size_t)r * wl.cap + slot] = v;
+  slot = wave_append(&c->medium_cnt[r], md, &any);
+  if (md) wl.medium[(size_t)r * wl.cap + slot] = v;
+  if (__ballot(lg)) {
+    const uint32_t nseg = lg ? (uint32_t)((deg + kSeg - 1) / kSeg) : 0u;
+    const uint32_t first = wave_reserve(&c->seg_count, nseg);
+    for (uint32_t t = 0; t < nseg; ++t) wl.segs[first + t] = make_uint2(v, t);
+  }
+}
+
+// Exclusive prefix of the kSubLists counters into LDS (pre[kSubLists] = total).
+// Called by every thread of the block; the first wave computes it.
+__device__ __forceinline__ void wl_prefix(const uint32_t* cnt, uint32_t* pre) {
+  if (threadIdx.x < 64) {
+    uint32_t total;
+    const uint32_t x = cnt[lane()];
+    pre[lane()] = wave_exclusive(x, &total);
+    if (lane() == 0) pre[kSubLists] = total;
+  }
+}
+// Entry i (< pre[kSubLists]) of the concatenated sub-lists.
+__device__ __forceinline__ uint32_t wl_get(const uint32_t* list, uint32_t cap, const uint32_t* pre,
+                                           uint32_t i) {
+  uint32_t lo = 0, hi = kSubLists;  // invariant pre[lo] <= i < pre[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return list[(size_t)lo * cap + (i - pre[lo])];
+}
+
 // --------------------------------------------------------------- setup
+// P[v] = v and empty forest slots, four vertices per lane with 16-byte stores;
+// block 0 also clears the control block.
+__global__ void k_init(Ctrl* c, uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv, int vec) {
+  if (blockIdx.x == 0) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(c);
+    for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      c->lmax = kEmpty;
+      c->bfs_source = kEmpty;
+      c->comp_min = kEmpty;
+    }
+  }
+  const uint64_t quads = vec ? n / 4 : 0;  // vec: P, fu, fv are 16-byte aligned
+  for (uint64_t q = gtid(); q < quads; q += wave_stride()) {
+    const uint32_t v = (uint32_t)(4 * q);
+    reinterpret_cast<uint4*>(P)[q] = make_uint4(v, v + 1, v + 2, v + 3);
+    if (fu) {
+      reinterpret_cast<uint4*>(fu)[q] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+      reinterpret_cast<uint4*>(fv)[q] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+    }
+  }
+  for (uint64_t v = 4 * quads + gtid(); v < n; v += wave_stride()) {
+    P[v] = (uint32_t)v;
+    if (fu) {
+      fu[v] = kEmpty;
+      fv[v] = kEmpty;
+    }
+  }
+}
+
 __global__ void k_ctrl_init(Ctrl* c) {
   uint32_t* w = reinterpret_cast<uint32_t*>(c);
   for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
@@ -95,28 +199,15 @@ __global__ void k_ctrl_init(Ctrl* c) {
 }
 
 __global__ void k_iota(uint32_t* P, uint32_t n) {
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride())
-    P[v] = (uint32_t)v;
+  for (uint64_t v = gtid(); v < n; v += wave_stride()) P[v] = (uint32_t)v;
 }
 
 __global__ void k_fill(uint32_t* p, uint32_t value, uint64_t count) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += wave_stride())
-    p[i] = value;
-}
-
-__global__ void k_init(uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv) {
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride()) {
-    P[v] = (uint32_t)v;
-    if (fu) {
-      fu[v] = kEmpty;
-      fv[v] = kEmpty;
-    }
-  }
+  for (uint64_t i = gtid(); i < count; i += wave_stride()) p[i] = value;
 }
 
 __global__ void k_copy(uint32_t* dst, const uint32_t* src, uint64_t count) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += wave_stride())
-    dst[i] = src[i];
+  for (uint64_t i = gtid(); i < count; i += wave_stride()) dst[i] = src[i];
 }
 
 template <typename OffT>
@@ -145,27 +236,235 @@ template <class R, typename OffT>
 __global__ void k_sample_kout(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
                               uint32_t n, uint32_t k, int random, uint64_t seed, LinkCtx lc,
                               Ctrl* stats) {
+  unsigned long long sampled = 0;
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    uint64_t v = base + lane();
-    uint32_t take = 0;
-    if (v < n) {
-      uint64_t b = off[v], deg = (uint64_t)off[v + 1] - b;
-      take = (uint32_t)(deg < k ? deg : k);
+    const uint64_t v = base + lane();
+    if (v >= n) continue;
+    const uint64_t b = off[v], deg = (uint64_t)off[v + 1] - b;
+    uint32_t take = (uint32_t)(deg < k ? deg : k);
+    if (!random) {
+      for (uint32_t j = 0; j < take; ++j) R::unite(lc, (uint32_t)v, nbrs[b + j]);
+    } else if (deg > 0) {
+      R::unite(lc, (uint32_t)v, nbrs[b]);
+      for (uint32_t j = 1; j < k; ++j) {
+        const uint32_t r = (uint32_t)(splitmix64_at(seed, v * k + j) >> 32);
+        const uint64_t pick = ((uint64_t)r * deg) >> 32;
+        R::unite(lc, (uint32_t)v, nbrs[b + pick]);
+      }
+      take = k;
+    }
+    sampled += take;
+  }
+  if (stats) {
+    // every lane of the wave left the loop after the same iterations
+    sampled = wave_sum(sampled);
+    if (lane() == 0 && sampled) atomicAdd(&stats->stat_sampled, sampled);
+  }
+}
+
+// Default k-out schedule: a persistent grid in which each lane walks vertices
+// v, v + T, v + 2T, ... (T = resident lanes, so every iteration of a wave
+// covers 64 consecutive vertices and their parent entries stay coalesced).
+// The next vertex's row bounds and leading neighbours are loaded before the
+// current vertex's unions run, so that random row-start fetch overlaps them.
+template <class R, typename OffT>
+__global__ void k_sample_kout_pf(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                                 uint32_t n, uint32_t k, int random, uint64_t seed, LinkCtx lc,
+                                 Ctrl* stats) {
+  const uint64_t T = wave_stride();
+  uint64_t v = gtid();
+  // row of v: start b, degree d, first two sampled neighbours
+  auto fetch = [&](uint64_t x, uint64_t& b, uint64_t& d, uint32_t& w0, uint32_t& w1) {
+    b = 0; d = 0; w0 = 0; w1 = 0;
+    if (x >= n) return;
+    b = off[x];
+    d = (uint64_t)off[x + 1] - b;
+    if (d > 0) w0 = nbrs[b];
+    if (k > 1 && d > 0) {
       if (!random) {
-        for (uint32_t j = 0; j < take; ++j) R::unite(lc, (uint32_t)v, nbrs[b + j]);
-      } else if (deg > 0) {
-        R::unite(lc, (uint32_t)v, nbrs[b]);
-        for (uint32_t j = 1; j < k; ++j) {
-          uint32_t r = (uint32_t)(splitmix64_at(seed, v * k + j) >> 32);
-          uint64_t pick = ((uint64_t)r * deg) >> 32;
-          R::unite(lc, (uint32_t)v, nbrs[b + pick]);
-        }
-        take = k;
+        if (d > 1) w1 = nbrs[b + 1];
+      } else {
+        const uint32_t r = (uint32_t)(splitmix64_at(seed, x * k + 1) >> 32);
+        w1 = nbrs[b + (((uint64_t)r * d) >> 32)];
       }
     }
-    if (stats) {
-      unsigned long long s = wave_sum(take);
-      if (lane() == 0 && s) atomicAdd(&stats->stat_sampled, s);
+  };
+  uint64_t b, d;
+  uint32_t w0, w1;
+  fetch(v, b, d, w0, w1);
+  unsigned long long sampled = 0;
+  while (v < n) {
+    const uint64_t nv = v + T;
+    uint64_t nb, nd;
+    uint32_t n0, n1;
+    fetch(nv, nb, nd, n0, n1);
+    if (d > 0) {
+      const uint32_t take = random ? k : (uint32_t)(d < k ? d : k);
+      R::unite(lc, (uint32_t)v, w0);
+      if (take > 1) R::unite(lc, (uint32_t)v, w1);
+      for (uint32_t j = 2; j < take; ++j) {
+        uint64_t pick = j;
+        if (random) pick = ((uint64_t)(uint32_t)(splitmix64_at(seed, v * k + j) >> 32) * d) >> 32;
+        R::unite(lc, (uint32_t)v, nbrs[b + pick]);
+      }
+      sampled += take;
+    }
+    v = nv;
+    b = nb;
+    d = nd;
+    w0 = n0;
+    w1 = n1;
+  }
+  if (stats) {
+    // lanes leave the loop at different iterations; they have reconverged here
+    sampled = wave_sum(sampled);
+    if (lane() == 0 && sampled) atomicAdd(&stats->stat_sampled, sampled);
+  }
+}
+
+// The same first-k sampling with Union-Rem-CAS as a lane-refill step machine
+// (uint32 offsets).  Each iteration: pick at most two addresses from the
+// lane's state, load them together, decide, issue at most one CAS, update the
+// state.  States: OFF (row bounds of the next vertex), NBR (its next two
+// sampled neighbours), REM (compare P[ru], P[rv]; hook ru if it is a root),
+// SPL (one splice step at ru: split or halve), CMP1/CMP2 (one FindSplit /
+// FindHalve step of the trailing compression of u, then of v).  Every state
+// either finishes a union, strictly lowers ru or the compression cursor, or
+// continues from a fresh CAS result, so each lane terminates.
+template <int F, int S>
+__global__ void __launch_bounds__(256) k_sample_kout_rem_sm(const uint32_t* __restrict__ off,
+                                                            const uint32_t* __restrict__ nbrs,
+                                                            uint32_t n, uint32_t k, LinkCtx lc,
+                                                            Ctrl* stats) {
+  enum : uint32_t { OFF, NBR, REM, SPL, CMP1, CMP2, DONE };
+  uint32_t* __restrict__ P = lc.P;
+  const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t chunk = (n + T - 1) / T;
+  uint64_t vtx = gtid() * chunk;
+  const uint64_t vend = min((uint64_t)n, vtx + chunk);
+  uint32_t st = vtx < vend ? OFF : DONE;
+  uint32_t b = 0, take = 0, j = 0, wnext = 0, have_next = 0;
+  uint32_t u = 0, v = 0, ru = 0, rv = 0, pru = 0, prv = 0, x = 0, xp = 0, side = 0;
+  unsigned long long sampled = 0, hooks = 0;
+  while (st != DONE) {
+    // ---- one load round
+    const uint32_t* a0;
+    const uint32_t* a1 = nullptr;
+    switch (st) {
+      case OFF: a0 = off + vtx; a1 = off + vtx + 1; break;
+      case NBR: a0 = nbrs + b + j; if (j + 1 < take) a1 = nbrs + b + j + 1; break;
+      case REM: a0 = P + ru; a1 = P + rv; break;
+      case SPL: a0 = P + pru; break;
+      case CMP1: a0 = P + x; break;
+      default: a0 = P + xp; break;  // CMP2
+    }
+    const uint32_t r0 = ld(a0);
+    const uint32_t r1 = a1 ? ld(a1) : 0u;
+    // ---- decide; at most one CAS (op: 0 none, 1 hook ru, 2 splice, 3 compression)
+    uint32_t op = 0;
+    bool union_end = false, cmp_end = false;
+    uint32_t* ca = nullptr;
+    uint32_t cexp = 0, cdes = 0;
+    switch (st) {
+      case OFF: {
+        const uint32_t deg = r1 - r0;
+        b = r0;
+        take = deg < k ? deg : k;
+        sampled += take;
+        j = 0;
+        if (take) st = NBR;
+        else if (++vtx >= vend) st = DONE;
+        break;
+      }
+      case NBR:
+        u = (uint32_t)vtx;
+        v = r0;
+        have_next = a1 != nullptr;
+        wnext = r1;
+        ru = u;
+        rv = v;
+        st = REM;
+        break;
+      case REM:
+        pru = r0;
+        prv = r1;
+        if (pru == prv) {
+          union_end = true;
+        } else {
+          if (pru < prv) {
+            uint32_t t = ru; ru = rv; rv = t;
+            t = pru; pru = prv; prv = t;
+          }
+          if (ru == pru) {
+            op = 1; ca = P + ru; cexp = ru; cdes = prv;
+          } else {
+            st = SPL;
+          }
+        }
+        break;
+      case SPL: {
+        const uint32_t w = r0;
+        if (w != pru) { op = 2; ca = P + ru; cexp = pru; cdes = w; }
+        ru = (S == kSpliceSplitOne) ? pru : w;
+        st = REM;
+        break;
+      }
+      case CMP1:
+        xp = r0;
+        if (xp == x) cmp_end = true;
+        else st = CMP2;
+        break;
+      default: {  // CMP2
+        const uint32_t w = r0;
+        if (w == xp) cmp_end = true;
+        else { op = 3; ca = P + x; cexp = xp; cdes = w; }
+        break;
+      }
+    }
+    uint32_t e = cexp;
+    bool ok = false;
+    if (op) ok = cas(ca, e, cdes);
+    // ---- transitions that need the CAS result
+    if (op == 1) {                    // hook attempt of root ru
+      if (ok) {
+        if (lc.fu) { lc.fu[ru] = u; lc.fv[ru] = v; }
+        ++hooks;
+        if constexpr (F != kFindNaive) { side = 0; x = u; st = CMP1; }
+        else union_end = true;
+      } else {
+        pru = e;                      // ru was linked meanwhile: splice from its fresh parent
+        st = SPL;
+      }
+    } else if (op == 3) {             // compression step done
+      x = (F == kFindSplit) ? xp : (ok ? cdes : e);
+      st = CMP1;
+    }
+    if (cmp_end) {
+      if (side == 0) { side = 1; x = v; st = CMP1; }
+      else union_end = true;
+    }
+    if (union_end) {
+      if (have_next) {
+        have_next = 0;
+        ++j;
+        v = wnext;
+        ru = u;
+        rv = v;
+        st = REM;
+      } else if (j + 1 < take) {
+        ++j;
+        st = NBR;
+      } else {
+        st = (++vtx < vend) ? OFF : DONE;
+      }
+    }
+  }
+  if (stats) {
+    sampled = wave_sum(sampled);
+    hooks = wave_sum(hooks);
+    if (lane() == 0) {
+      if (sampled) atomicAdd(&stats->stat_sampled, sampled);
+      if (hooks && lc.hooks) atomicAdd(lc.hooks, hooks);
     }
   }
 }
@@ -223,21 +522,10 @@ __global__ void k_hb_step2(const OffT* __restrict__ off, const uint32_t* __restr
   }
 }
 
-// Full compression: P[v] = root(v) for all v (pointer jumping).  Runs after a
-// kernel boundary with no concurrent links, so plain loads are exact enough:
-// any value read is an ancestor.
-__global__ void k_compress(uint32_t* P, uint32_t* out, uint32_t n) {
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride()) {
-    uint32_t p = P[v];
-    uint32_t r = p;
-    if (p != v) r = root_plain(P, p);
-    if (out != P || r != p) out[v] = r;
-  }
-}
-
 // GetMostFrequentLabel over a seeded sample of vertices: sample j is vertex
-// floor(hi32(SplitMix64_j(seed)) * n / 2^32).  Counts go to an LDS hash table;
-// the winner is the largest count, smallest label on ties.
+// floor(hi32(SplitMix64_j(seed)) * n / 2^32), its label the root of its tree
+// (so no full compression has to precede it).  Counts go to an LDS hash
+// table; the winner is the largest count, smallest label on ties.
 constexpr uint32_t kLmaxTable = 2 * kMaxLmaxSamples;
 __global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, uint32_t samples,
                                                uint64_t seed, Ctrl* c) {
@@ -251,12 +539,12 @@ __global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, ui
   if (threadIdx.x == 0) best = 0;
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < samples; j += blockDim.x) {
-    uint32_t hi = (uint32_t)(splitmix64_at(seed, j) >> 32);
-    uint32_t v = (uint32_t)(((uint64_t)hi * n) >> 32);
-    uint32_t label = P[v];
+    const uint32_t hi = (uint32_t)(splitmix64_at(seed, j) >> 32);
+    const uint32_t v = (uint32_t)(((uint64_t)hi * n) >> 32);
+    const uint32_t label = root_plain(P, v);
     uint32_t h = (label * 2654435761u) & (kLmaxTable - 1);
     for (;;) {
-      uint32_t prev = atomicCAS(&keys[h], kEmpty, label);
+      const uint32_t prev = atomicCAS(&keys[h], kEmpty, label);
       if (prev == kEmpty || prev == label) {
         atomicAdd(&cnts[h], 1u);
         break;
@@ -268,7 +556,7 @@ __global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, ui
   unsigned long long mine = 0;
   for (uint32_t i = threadIdx.x; i < kLmaxTable; i += blockDim.x)
     if (keys[i] != kEmpty) {
-      unsigned long long key = ((unsigned long long)cnts[i] << 32) | (kEmpty - keys[i]);
+      const unsigned long long key = ((unsigned long long)cnts[i] << 32) | (kEmpty - keys[i]);
       mine = key > mine ? key : mine;
     }
   mine = wave_max(mine);
@@ -277,91 +565,147 @@ __global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, ui
   if (threadIdx.x == 0 && best) c->lmax = kEmpty - (uint32_t)(best & 0xFFFFFFFFu);
 }
 
-// --------------------------------------------------------------- gathering
-// Vertex gathering: active = degree > 0 and label != L_max (L_max = kEmpty
-// when there was no sampling, so every vertex with edges is active).
+// Full compression fused with vertex gathering.  mode 0: no sampling (P is the
+// identity, every vertex with edges is active); mode 1: P is already flat
+// (BFS sampling); mode 2: P[v] = root(v) first (k-out, hook-based).  Active:
+// degree > 0 and label != L_max (unless skip_lmax is 0).
 template <typename OffT>
-__global__ void k_gather(const OffT* __restrict__ off, const uint32_t* __restrict__ P, uint32_t n,
-                         Ctrl* c, uint32_t* small, uint2* segs, int want_stats, int skip_lmax) {
+__global__ void k_compress_gather(const OffT* __restrict__ off, uint32_t* P, uint32_t n, Ctrl* c,
+                                  WorkLists wl, int mode, int skip_lmax, int want_stats) {
   const uint32_t lmax = skip_lmax ? c->lmax : kEmpty;
+  unsigned long long act = 0, edges = 0;
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    uint64_t v = base + lane();
+    const uint64_t v = base + lane();
     uint64_t deg = 0;
     bool active = false;
     if (v < n) {
       deg = (uint64_t)off[v + 1] - off[v];
-      active = deg > 0 && P[v] != lmax;
-    }
-    bool is_small = active && deg <= kSmallDeg;
-    uint32_t nseg = (active && !is_small) ? (uint32_t)((deg + kSeg - 1) / kSeg) : 0;
-    uint32_t slot = wave_reserve(&c->small_count, is_small ? 1u : 0u);
-    if (is_small) small[slot] = (uint32_t)v;
-    uint32_t sbase = wave_reserve(&c->seg_count, nseg);
-    for (uint32_t t = 0; t < nseg; ++t) segs[sbase + t] = make_uint2((uint32_t)v, t);
-    if (want_stats) {
-      unsigned long long a = wave_sum(active ? 1 : 0), e = wave_sum(active ? deg : 0);
-      if (lane() == 0) {
-        if (a) atomicAdd(&c->stat_active, a);
-        if (e) atomicAdd(&c->stat_finish_edges, e);
+      uint32_t r = (uint32_t)v;
+      if (mode != 0) {
+        const uint32_t p = P[v];
+        r = p;
+        if (mode == 2 && p != v) {
+          r = root_plain(P, p);
+          if (r != p) P[v] = r;
+        }
       }
+      active = deg > 0 && r != lmax;
+    }
+    wl_push(wl, c, base >> 6, (uint32_t)v, deg, active);
+    act += active ? 1 : 0;
+    edges += active ? deg : 0;
+  }
+  if (want_stats) {
+    act = wave_sum(act);
+    edges = wave_sum(edges);
+    if (lane() == 0) {
+      if (act) atomicAdd(&c->stat_active, act);
+      if (edges) atomicAdd(&c->stat_finish_edges, edges);
     }
   }
 }
 
-// --------------------------------------------------------------- finish (union-find)
-// Alg. union-find meta-algorithm: every edge (u, v) of every active u is united.
+// Finish phase for the union-find rules (Alg. union-find meta-algorithm):
+// every edge (u, v) of every active u is united.  Small vertices one lane
+// each, medium vertices one wave each, hub segments one wave each.
 template <class R, typename OffT>
-__global__ void k_finish_small(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                               const uint32_t* __restrict__ small, const Ctrl* c, LinkCtx lc) {
-  const uint32_t count = c->small_count;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += wave_stride()) {
-    uint32_t u = small[i];
-    uint64_t b = off[u], e = off[u + 1];
-    for (uint64_t x = b; x < e; ++x) R::unite(lc, u, nbrs[x]);
+__global__ void k_finish(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                         WorkLists wl, const Ctrl* c, LinkCtx lc) {
+  __shared__ uint32_t pre_s[kSubLists + 1], pre_m[kSubLists + 1];
+  wl_prefix(c->small_cnt, pre_s);
+  wl_prefix(c->medium_cnt, pre_m);
+  __syncthreads();
+  const uint32_t S = pre_s[kSubLists], M = pre_m[kSubLists], G = c->seg_count;
+  for (uint64_t i = gtid(); i < S; i += wave_stride()) {
+    const uint32_t u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
+    const uint64_t e = off[u + 1];
+    for (uint64_t x = off[u]; x < e; ++x) R::unite(lc, u, nbrs[x]);
   }
-}
-
-template <class R, typename OffT>
-__global__ void k_finish_segs(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                              const uint2* __restrict__ segs, const Ctrl* c, LinkCtx lc) {
-  const uint32_t count = c->seg_count;
-  for (uint64_t s = wave_index(); s < count; s += wave_count()) {
-    uint2 sg = segs[s];
-    uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
+  for (uint64_t w = wave_index(); w < M; w += wave_count()) {
+    const uint32_t u = wl_get(wl.medium, wl.cap, pre_m, (uint32_t)w);
+    const uint64_t e = off[u + 1];
+    for (uint64_t x = off[u] + lane(); x < e; x += 64) R::unite(lc, u, nbrs[x]);
+  }
+  for (uint64_t s = wave_index(); s < G; s += wave_count()) {
+    const uint2 sg = wl.segs[s];
+    const uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
     uint64_t e = off[sg.x + 1];
     if (e > b + kSeg) e = b + kSeg;
     for (uint64_t x = b + lane(); x < e; x += 64) R::unite(lc, sg.x, nbrs[x]);
   }
 }
 
+// Label finalisation: labels[v] = root(v).  When sampling ran and the L_max
+// root is still a root, only the active vertices can have a changed root (the
+// L_max group points at it, isolated vertices are their own roots), so only
+// the work lists are finalised; otherwise every vertex is.
+__global__ void k_finalize(uint32_t* P, uint32_t n, const Ctrl* c, WorkLists wl, int sampled) {
+  __shared__ uint32_t pre_s[kSubLists + 1], pre_m[kSubLists + 1];
+  wl_prefix(c->small_cnt, pre_s);
+  wl_prefix(c->medium_cnt, pre_m);
+  __syncthreads();
+  const uint32_t lmax = c->lmax;
+  const bool partial = sampled && lmax != kEmpty && lmax < n && P[lmax] == lmax;
+  if (partial) {
+    const uint32_t S = pre_s[kSubLists], M = pre_m[kSubLists], G = c->seg_count;
+    const uint64_t total = (uint64_t)S + M + G;
+    for (uint64_t i = gtid(); i < total; i += wave_stride()) {
+      uint32_t a;
+      if (i < S) a = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
+      else if (i < (uint64_t)S + M) a = wl_get(wl.medium, wl.cap, pre_m, (uint32_t)(i - S));
+      else {
+        const uint2 sg = wl.segs[i - S - M];
+        if (sg.y != 0) continue;
+        a = sg.x;
+      }
+      const uint32_t p = P[a];
+      const uint32_t r = root_plain(P, p);
+      if (r != p) P[a] = r;
+    }
+  } else {
+    for (uint64_t v = gtid(); v < n; v += wave_stride()) {
+      const uint32_t p = P[v];
+      if (p == v) continue;
+      const uint32_t r = root_plain(P, p);
+      if (r != p) P[v] = r;
+    }
+  }
+}
+
+// labels_out[v] = root(v) into a separate buffer (incremental labels).
+__global__ void k_compress_to(const uint32_t* P, uint32_t* out, uint32_t n) {
+  for (uint64_t v = gtid(); v < n; v += wave_stride()) out[v] = root_plain(P, (uint32_t)v);
+}
+
 // COO finish (no sampling for COO): one lane per edge.
 template <class R>
 __global__ void k_unite_pairs(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
                               uint64_t m, LinkCtx lc) {
-  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += wave_stride())
-    R::unite(lc, a[e], b[e]);
+  for (uint64_t e = gtid(); e < m; e += wave_stride()) R::unite(lc, a[e], b[e]);
 }
 
 // --------------------------------------------------------------- materialised edges
 // SV, LT and LP iterate over the active edges many times; they are laid out
 // once as a COO pair list (one entry per CSR entry of an active vertex).
 template <typename OffT>
-__global__ void k_materialize_small(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                                    const uint32_t* __restrict__ small, Ctrl* c, uint32_t* esrc,
-                                    uint32_t* edst) {
-  const uint32_t count = c->small_count;
-  for (uint64_t base = wave_base(); base < count; base += wave_stride()) {
-    uint64_t i = base + lane();
+__global__ void k_materialize(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                              WorkLists wl, Ctrl* c, uint32_t* esrc, uint32_t* edst) {
+  __shared__ uint32_t pre_s[kSubLists + 1], pre_m[kSubLists + 1];
+  wl_prefix(c->small_cnt, pre_s);
+  wl_prefix(c->medium_cnt, pre_m);
+  __syncthreads();
+  const uint32_t S = pre_s[kSubLists], M = pre_m[kSubLists], G = c->seg_count;
+  for (uint64_t base = wave_base(); base < S; base += wave_stride()) {
+    const uint64_t i = base + lane();
     uint32_t u = 0, deg = 0;
     uint64_t b = 0;
-    if (i < count) {
-      u = small[i];
+    if (i < S) {
+      u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
       b = off[u];
       deg = (uint32_t)((uint64_t)off[u + 1] - b);
     }
     uint32_t total;
-    uint32_t o = wave_exclusive(deg, &total);
+    const uint32_t o = wave_exclusive(deg, &total);
     unsigned long long pos = 0;
     if (total && lane() == 0) pos = atomicAdd(&c->edge_count, (unsigned long long)total);
     pos = __shfl(pos, 0) + o;
@@ -370,23 +714,25 @@ __global__ void k_materialize_small(const OffT* __restrict__ off, const uint32_t
       edst[pos + j] = nbrs[b + j];
     }
   }
-}
-
-template <typename OffT>
-__global__ void k_materialize_segs(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                                   const uint2* __restrict__ segs, Ctrl* c, uint32_t* esrc,
-                                   uint32_t* edst) {
-  const uint32_t count = c->seg_count;
-  for (uint64_t s = wave_index(); s < count; s += wave_count()) {
-    uint2 sg = segs[s];
-    uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
-    uint64_t e = off[sg.x + 1];
-    if (e > b + kSeg) e = b + kSeg;
+  for (uint64_t w = wave_index(); w < (uint64_t)M + G; w += wave_count()) {
+    uint32_t u;
+    uint64_t b, e;
+    if (w < M) {
+      u = wl_get(wl.medium, wl.cap, pre_m, (uint32_t)w);
+      b = off[u];
+      e = off[u + 1];
+    } else {
+      const uint2 sg = wl.segs[w - M];
+      u = sg.x;
+      b = (uint64_t)off[u] + (uint64_t)sg.y * kSeg;
+      e = off[u + 1];
+      if (e > b + kSeg) e = b + kSeg;
+    }
     unsigned long long pos = 0;
     if (lane() == 0) pos = atomicAdd(&c->edge_count, (unsigned long long)(e - b));
     pos = __shfl(pos, 0);
     for (uint64_t x = b + lane(); x < e; x += 64) {
-      esrc[pos + (x - b)] = sg.x;
+      esrc[pos + (x - b)] = u;
       edst[pos + (x - b)] = nbrs[x];
     }
   }
@@ -394,9 +740,8 @@ __global__ void k_materialize_segs(const OffT* __restrict__ off, const uint32_t*
 
 __global__ void k_materialize_coo(const uint32_t* a, const uint32_t* b, uint64_t m, Ctrl* c,
                                   uint32_t* esrc, uint32_t* edst) {
-  uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid == 0) c->edge_count = m;
-  for (uint64_t e = tid; e < m; e += wave_stride()) {
+  if (gtid() == 0) c->edge_count = m;
+  for (uint64_t e = gtid(); e < m; e += wave_stride()) {
     esrc[e] = a[e];
     edst[e] = b[e];
   }
@@ -593,7 +938,6 @@ __global__ void k_lp_round(const uint32_t* __restrict__ esrc, const uint32_t* __
   if (any) mark_changed(c, slot);
 }
 
-// --------------------------------------------------------------- BFS sampling
 template <typename OffT>
 __global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) {
   unsigned long long best = 0;
@@ -630,107 +974,135 @@ __global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* vis
 }
 
 __global__ void k_bfs_level_reset(Ctrl* c, uint32_t nxt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (blockIdx.x != 0) return;
+  for (uint32_t i = threadIdx.x; i < kSubLists; i += blockDim.x) {
+    c->small_cnt[i] = 0;
+    c->medium_cnt[i] = 0;
+  }
+  if (threadIdx.x == 0) {
     c->frontier_count[nxt] = 0;
     c->frontier_edges[nxt] = 0;
-    c->small_count = 0;
     c->seg_count = 0;
+    c->queue_cursor = 0;
   }
 }
 
-// Top-down: split the frontier queue into small vertices and segments.
+// Top-down: sort the frontier queue into the work classes.
 template <typename OffT>
 __global__ void k_bfs_td_split(const OffT* __restrict__ off, const uint32_t* __restrict__ queue,
-                               Ctrl* c, uint32_t cur, uint32_t* small, uint2* segs) {
+                               Ctrl* c, uint32_t cur, WorkLists wl) {
   const uint32_t count = c->frontier_count[cur];
   for (uint64_t base = wave_base(); base < count; base += wave_stride()) {
-    uint64_t i = base + lane();
+    const uint64_t i = base + lane();
     uint32_t u = 0;
     uint64_t deg = 0;
     if (i < count) {
       u = queue[i];
       deg = (uint64_t)off[u + 1] - off[u];
     }
-    bool is_small = i < count && deg > 0 && deg <= kSmallDeg;
-    uint32_t nseg = (i < count && deg > kSmallDeg) ? (uint32_t)((deg + kSeg - 1) / kSeg) : 0;
-    uint32_t slot = wave_reserve(&c->small_count, is_small ? 1u : 0u);
-    if (is_small) small[slot] = u;
-    uint32_t sb = wave_reserve(&c->seg_count, nseg);
-    for (uint32_t t = 0; t < nseg; ++t) segs[sb + t] = make_uint2(u, t);
+    wl_push(wl, c, base >> 6, u, deg, i < count && deg > 0);
+  }
+}
+
+// Visit w from u: claim its visited bit; new vertices are appended to the next
+// queue (one atomic per wave) and record their BFS-tree edge.  All 64 lanes
+// must be active; `valid` masks the lanes without an edge this round.
+template <typename OffT>
+__device__ __forceinline__ void bfs_visit(const OffT* __restrict__ off, bool valid, uint32_t u,
+                                          uint32_t w, uint32_t* visited, uint32_t* queue_out,
+                                          Ctrl* c, uint32_t nxt, uint32_t* fu, uint32_t* fv,
+                                          unsigned long long* edges) {
+  bool fresh = false;
+  if (valid) {
+    const uint32_t bit = 1u << (w & 31);
+    if (!(ld(&visited[w >> 5]) & bit)) fresh = !(atomicOr(&visited[w >> 5], bit) & bit);
+  }
+  bool any;
+  const uint32_t slot = wave_append(&c->frontier_count[nxt], fresh, &any);
+  if (fresh) {
+    queue_out[slot] = w;
+    *edges += (uint64_t)off[w + 1] - off[w];
+    if (fu) {
+      fu[w] = u;
+      fv[w] = w;
+    }
   }
 }
 
 template <typename OffT>
-__device__ __forceinline__ void bfs_visit_td(const OffT* __restrict__ off, uint32_t u, uint32_t w,
-                                             uint32_t* visited, uint32_t* queue_out, Ctrl* c,
-                                             uint32_t nxt, uint32_t* fu, uint32_t* fv) {
-  uint32_t bit = 1u << (w & 31);
-  if (ld(&visited[w >> 5]) & bit) return;
-  uint32_t old = atomicOr(&visited[w >> 5], bit);
-  if (old & bit) return;
-  uint32_t pos = atomicAdd(&c->frontier_count[nxt], 1u);
-  queue_out[pos] = w;
-  uint64_t deg = (uint64_t)off[w + 1] - off[w];
-  atomicAdd(&c->frontier_edges[nxt], (unsigned long long)deg);
-  atomicAdd(&c->explored_edges, (unsigned long long)deg);
-  if (fu) {
-    fu[w] = u;
-    fv[w] = w;
+__global__ void k_bfs_td(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                         WorkLists wl, Ctrl* c, uint32_t nxt, uint32_t* visited,
+                         uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
+  __shared__ uint32_t pre_s[kSubLists + 1], pre_m[kSubLists + 1];
+  wl_prefix(c->small_cnt, pre_s);
+  wl_prefix(c->medium_cnt, pre_m);
+  __syncthreads();
+  const uint32_t S = pre_s[kSubLists], M = pre_m[kSubLists], G = c->seg_count;
+  unsigned long long edges = 0;
+  for (uint64_t base = wave_base(); base < S; base += wave_stride()) {
+    const uint64_t i = base + lane();
+    uint32_t u = 0;
+    uint64_t b = 0, deg = 0;
+    if (i < S) {
+      u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
+      b = off[u];
+      deg = (uint64_t)off[u + 1] - b;
+    }
+    for (uint32_t j = 0; __ballot(j < deg); ++j) {
+      const bool valid = j < deg;
+      bfs_visit(off, valid, u, valid ? nbrs[b + j] : 0u, visited, queue_out, c, nxt, fu, fv,
+                &edges);
+    }
   }
-}
-
-template <typename OffT>
-__global__ void k_bfs_td_small(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                               const uint32_t* __restrict__ small, Ctrl* c, uint32_t nxt,
-                               uint32_t* visited, uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
-  const uint32_t count = c->small_count;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += wave_stride()) {
-    uint32_t u = small[i];
-    for (uint64_t x = off[u]; x < (uint64_t)off[u + 1]; ++x)
-      bfs_visit_td(off, u, nbrs[x], visited, queue_out, c, nxt, fu, fv);
+  for (uint64_t w = wave_index(); w < (uint64_t)M + G; w += wave_count()) {
+    uint32_t u;
+    uint64_t b, e;
+    if (w < M) {
+      u = wl_get(wl.medium, wl.cap, pre_m, (uint32_t)w);
+      b = off[u];
+      e = off[u + 1];
+    } else {
+      const uint2 sg = wl.segs[w - M];
+      u = sg.x;
+      b = (uint64_t)off[u] + (uint64_t)sg.y * kSeg;
+      e = off[u + 1];
+      if (e > b + kSeg) e = b + kSeg;
+    }
+    for (uint64_t x0 = b; x0 < e; x0 += 64) {
+      const uint64_t x = x0 + lane();
+      const bool valid = x < e;
+      bfs_visit(off, valid, u, valid ? nbrs[x] : 0u, visited, queue_out, c, nxt, fu, fv, &edges);
+    }
   }
-}
-
-template <typename OffT>
-__global__ void k_bfs_td_segs(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                              const uint2* __restrict__ segs, Ctrl* c, uint32_t nxt,
-                              uint32_t* visited, uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
-  const uint32_t count = c->seg_count;
-  for (uint64_t s = wave_index(); s < count; s += wave_count()) {
-    uint2 sg = segs[s];
-    uint64_t b = (uint64_t)off[sg.x] + (uint64_t)sg.y * kSeg;
-    uint64_t e = off[sg.x + 1];
-    if (e > b + kSeg) e = b + kSeg;
-    for (uint64_t x = b + lane(); x < e; x += 64)
-      bfs_visit_td(off, sg.x, nbrs[x], visited, queue_out, c, nxt, fu, fv);
+  edges = wave_sum(edges);
+  if (lane() == 0 && edges) {
+    atomicAdd(&c->frontier_edges[nxt], edges);
+    atomicAdd(&c->explored_edges, edges);
   }
 }
 
 __global__ void k_queue_to_bits(const uint32_t* __restrict__ queue, const Ctrl* c, uint32_t cur,
                                 uint32_t* bits) {
   const uint32_t count = c->frontier_count[cur];
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += wave_stride()) {
-    uint32_t w = queue[i];
+  for (uint64_t i = gtid(); i < count; i += wave_stride()) {
+    const uint32_t w = queue[i];
     atomicOr(&bits[w >> 5], 1u << (w & 31));
   }
 }
 
+// Rebuild a frontier queue from its bitmap (queue_cursor is the append cursor).
 __global__ void k_bits_to_queue(const uint32_t* __restrict__ bits, uint32_t words, Ctrl* c,
-                                uint32_t slot_counter, uint32_t* queue) {
-  // counts are already known; rebuild the queue from the bitmap into slot order
+                                uint32_t* queue) {
   for (uint64_t base = wave_base(); base < words; base += wave_stride()) {
-    uint64_t i = base + lane();
+    const uint64_t i = base + lane();
     uint32_t word = i < words ? bits[i] : 0u;
-    uint32_t pos = wave_reserve(&c->small_count, (uint32_t)__popc(word));
+    uint32_t pos = wave_reserve(&c->queue_cursor, (uint32_t)__popc(word));
     while (word) {
-      uint32_t b = __ffs(word) - 1;
+      const uint32_t b = __ffs(word) - 1;
       queue[pos++] = (uint32_t)(i * 32 + b);
       word &= word - 1;
     }
   }
-  (void)slot_counter;
 }
 
 // Bottom-up: every unvisited vertex looks for a neighbour in the frontier.
@@ -738,14 +1110,13 @@ template <typename OffT>
 __global__ void k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
                          uint32_t n, uint32_t* visited, const uint32_t* __restrict__ fr_in,
                          uint32_t* fr_out, Ctrl* c, uint32_t nxt, uint32_t* fu, uint32_t* fv) {
-  uint32_t found = 0;
-  unsigned long long found_edges = 0;
+  unsigned long long found = 0, found_edges = 0;
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    uint64_t v = base + lane();
+    const uint64_t v = base + lane();
     if (v < n && !(visited[v >> 5] & (1u << (v & 31)))) {
-      uint64_t b = off[v], e = off[v + 1];
+      const uint64_t b = off[v], e = off[v + 1];
       for (uint64_t x = b; x < e; ++x) {
-        uint32_t w = nbrs[x];
+        const uint32_t w = nbrs[x];
         if (fr_in[w >> 5] & (1u << (w & 31))) {
           atomicOr(&visited[v >> 5], 1u << (v & 31));
           atomicOr(&fr_out[v >> 5], 1u << (v & 31));
@@ -760,8 +1131,10 @@ __global__ void k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restric
       }
     }
   }
-  if (found) {
-    atomicAdd(&c->frontier_count[nxt], found);
+  found = wave_sum(found);
+  found_edges = wave_sum(found_edges);
+  if (lane() == 0 && found) {
+    atomicAdd(&c->frontier_count[nxt], (uint32_t)found);
     atomicAdd(&c->frontier_edges[nxt], found_edges);
     atomicAdd(&c->explored_edges, found_edges);
   }
@@ -788,9 +1161,9 @@ __global__ void k_bfs_label(const uint32_t* __restrict__ visited, uint32_t n, co
 template <class R>
 __global__ void k_query(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint64_t q,
                         uint32_t* P, uint8_t* out) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += wave_stride()) {
-    uint32_t ra = find<R::kFind>(P, a[i]);
-    uint32_t rb = find<R::kFind>(P, b[i]);
+  for (uint64_t i = gtid(); i < q; i += wave_stride()) {
+    const uint32_t ra = find<R::kFind>(P, a[i]);
+    const uint32_t rb = find<R::kFind>(P, b[i]);
     out[i] = (uint8_t)(ra == rb);
   }
 }
@@ -798,7 +1171,33 @@ __global__ void k_query(const uint32_t* __restrict__ a, const uint32_t* __restri
 // =============================================================== host side
 namespace {
 
-constexpr uint32_t kPersistentBlocks = 2048;  // 256 CUs x 8 resident workgroups
+// Resident workgroups for a persistent launch of `kernel` (all CUs x what the
+// occupancy calculator allows), cached per kernel and block size.
+template <class K>
+uint32_t persistent_grid(K kernel, uint32_t block) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void*, uint32_t>, uint32_t>> cache;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : cache)
+    if (e.first.first == key && e.first.second == block) return e.second;
+  int dev = 0, cus = 256, per_cu = 8;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, 0) != hipSuccess ||
+      per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  const uint32_t g = (uint32_t)cus * (uint32_t)per_cu;
+  cache.push_back({{key, block}, g});
+  return g;
+}
+
+constexpr uint32_t kPersistentBlocks = 2048;  // round kernels: 256 CUs x 8 workgroups
 
 template <class Fn>
 gconn_status with_rule(int link, int find_rule, int splice, Fn&& fn) {
@@ -858,8 +1257,7 @@ struct Run {
   hipStream_t s;
   uint32_t block;
   Ctrl* ctrl;
-  uint32_t* small;
-  uint2* segs;
+  WorkLists wl;
   uint32_t* hooks;
   uint64_t rounds = 0;
 
@@ -868,8 +1266,10 @@ struct Run {
       : g(g_), P(P_), fu(fu_), fv(fv_), ws(ws_), L(L_), o(o_), want_stats(st), s(s_) {
     block = (uint32_t)o.block;
     ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
-    small = reinterpret_cast<uint32_t*>(ws + L.small);
-    segs = reinterpret_cast<uint2*>(ws + L.segs);
+    wl.small = reinterpret_cast<uint32_t*>(ws + L.small);
+    wl.medium = reinterpret_cast<uint32_t*>(ws + L.medium);
+    wl.segs = reinterpret_cast<uint2*>(ws + L.segs);
+    wl.cap = L.sub_cap;
     hooks = (o.link == GCONN_LINK_HOOKS) ? reinterpret_cast<uint32_t*>(ws + L.hooks) : nullptr;
   }
 
@@ -906,6 +1306,11 @@ struct Run {
     return GCONN_OK;
   }
 
+  // Union-Rem-CAS first-k sampling as a step machine (uint32 offsets only).
+  bool kout_step_machine() const {
+    return o.link == GCONN_LINK_REM_CAS && !o.kout_random && !g.offsets_64 && o.schedule == 2;
+  }
+
   template <typename OffT>
   gconn_status sample_phase() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
@@ -913,13 +1318,34 @@ struct Run {
     Ctrl* st = want_stats ? ctrl : nullptr;
     GCONN_TRY(prof_mark(kPhaseSample, true, s));
     if (o.sample == GCONN_SAMPLE_KOUT) {
-      GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
-        using R = decltype(rule);
-        k_sample_kout<R, OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, n, o.k, o.kout_random,
-                                                          o.seed ^ 0x6b6f7574ull, link_ctx(), st);
-        GCONN_LAUNCHED("k_sample_kout");
-        return GCONN_OK;
-      }));
+      if (kout_step_machine()) {
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          auto kern = k_sample_kout_rem_sm<R::kFind, R::kSplice>;
+          const uint32_t grid = persistent_grid(kern, 256);
+          kern<<<grid, 256, 0, s>>>(static_cast<const uint32_t*>(g.offsets), g.nbrs, n, o.k,
+                                    link_ctx(), st);
+          GCONN_LAUNCHED("k_sample_kout_rem_sm");
+          return GCONN_OK;
+        }));
+      } else if (o.schedule == 1) {
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          k_sample_kout<R, OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, n, o.k, o.kout_random,
+                                                            o.seed ^ 0x6b6f7574ull, link_ctx(), st);
+          GCONN_LAUNCHED("k_sample_kout");
+          return GCONN_OK;
+        }));
+      } else {
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          const uint32_t grid = persistent_grid(k_sample_kout_pf<R, OffT>, block);
+          k_sample_kout_pf<R, OffT><<<grid, block, 0, s>>>(off, g.nbrs, n, o.k, o.kout_random,
+                                                           o.seed ^ 0x6b6f7574ull, link_ctx(), st);
+          GCONN_LAUNCHED("k_sample_kout_pf");
+          return GCONN_OK;
+        }));
+      }
     } else if (o.sample == GCONN_SAMPLE_HB) {
       k_hb_step1<OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, P, n, fu, fv, st);
       GCONN_LAUNCHED("k_hb_step1");
@@ -933,12 +1359,6 @@ struct Run {
       GCONN_TRY(bfs_phase<OffT>());
     }
     GCONN_TRY(prof_mark(kPhaseSample, false, s));
-    if (o.sample != GCONN_SAMPLE_BFS) {
-      GCONN_TRY(prof_mark(kPhaseCompress, true, s));
-      k_compress<<<gridN(n), block, 0, s>>>(P, P, n);
-      GCONN_LAUNCHED("k_compress");
-      GCONN_TRY(prof_mark(kPhaseCompress, false, s));
-    }
     GCONN_TRY(prof_mark(kPhaseLmax, true, s));
     k_lmax<<<1, 1024, 0, s>>>(P, n, o.lmax_samples, o.seed, ctrl);
     GCONN_LAUNCHED("k_lmax");
@@ -967,6 +1387,7 @@ struct Run {
     bool bottom_up = false;
     bool have_queue = true;  // frontier `cur` is held as a queue (else as bits)
     Ctrl h;
+    const uint32_t td_grid = persistent_grid(k_bfs_td<OffT>, block);
     for (uint32_t level = 0;; ++level) {
       const uint32_t cur = level & 1, nxt = cur ^ 1;
       GCONN_TRY(read_ctrl(&h));
@@ -976,7 +1397,7 @@ struct Run {
       const double m_u = (double)g.m - (double)h.explored_edges;
       if (!bottom_up && m_f > m_u / alpha) bottom_up = true;
       else if (bottom_up && (double)h.frontier_count[cur] < (double)n / beta) bottom_up = false;
-      k_bfs_level_reset<<<1, 64, 0, s>>>(ctrl, nxt);
+      k_bfs_level_reset<<<1, 128, 0, s>>>(ctrl, nxt);
       GCONN_LAUNCHED("k_bfs_level_reset");
       if (bottom_up) {
         if (have_queue) {
@@ -994,21 +1415,15 @@ struct Run {
         have_queue = false;
       } else {
         if (!have_queue) {
-          // rebuild the queue of `cur` from its bitmap (small_count is the cursor)
-          k_bits_to_queue<<<gridN(words), block, 0, s>>>(bits[cur], words, ctrl, cur, queue[cur]);
+          k_bits_to_queue<<<gridN(words), block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
           GCONN_LAUNCHED("k_bits_to_queue");
-          k_bfs_level_reset<<<1, 64, 0, s>>>(ctrl, nxt);
-          GCONN_LAUNCHED("k_bfs_level_reset");
         }
         k_bfs_td_split<OffT><<<gridN(h.frontier_count[cur]), block, 0, s>>>(off, queue[cur], ctrl,
-                                                                             cur, small, segs);
+                                                                             cur, wl);
         GCONN_LAUNCHED("k_bfs_td_split");
-        k_bfs_td_small<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, small, ctrl, nxt,
-                                                                 visited, queue[nxt], fu, fv);
-        GCONN_LAUNCHED("k_bfs_td_small");
-        k_bfs_td_segs<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, segs, ctrl, nxt,
-                                                                visited, queue[nxt], fu, fv);
-        GCONN_LAUNCHED("k_bfs_td_segs");
+        k_bfs_td<OffT><<<td_grid, block, 0, s>>>(off, g.nbrs, wl, ctrl, nxt, visited, queue[nxt],
+                                                 fu, fv);
+        GCONN_LAUNCHED("k_bfs_td");
         have_queue = true;
       }
     }
@@ -1016,8 +1431,8 @@ struct Run {
     GCONN_LAUNCHED("k_bfs_min");
     k_bfs_label<<<gridN(n), block, 0, s>>>(visited, n, ctrl, P);
     GCONN_LAUNCHED("k_bfs_label");
-    // the gather lists were used as scratch: reset their counters
-    k_bfs_level_reset<<<1, 64, 0, s>>>(ctrl, 0);
+    // the work lists were used as scratch: clear their counters
+    k_bfs_level_reset<<<1, 128, 0, s>>>(ctrl, 0);
     GCONN_LAUNCHED("k_bfs_level_reset");
     return GCONN_OK;
   }
@@ -1025,9 +1440,10 @@ struct Run {
   template <typename OffT>
   gconn_status gather() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
-    k_gather<OffT><<<gridN(g.n), block, 0, s>>>(off, P, g.n, ctrl, small, segs, want_stats ? 1 : 0,
-                                                skip_lmax() ? 1 : 0);
-    GCONN_LAUNCHED("k_gather");
+    const int mode = o.sample == GCONN_SAMPLE_NONE ? 0 : (o.sample == GCONN_SAMPLE_BFS ? 1 : 2);
+    k_compress_gather<OffT><<<gridN(g.n), block, 0, s>>>(off, P, g.n, ctrl, wl, mode,
+                                                         skip_lmax() ? 1 : 0, want_stats ? 1 : 0);
+    GCONN_LAUNCHED("k_compress_gather");
     return GCONN_OK;
   }
 
@@ -1036,12 +1452,9 @@ struct Run {
     const OffT* off = static_cast<const OffT*>(g.offsets);
     return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
       using R = decltype(rule);
-      k_finish_small<R, OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, small, ctrl,
-                                                                  link_ctx());
-      GCONN_LAUNCHED("k_finish_small");
-      k_finish_segs<R, OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, segs, ctrl,
-                                                                 link_ctx());
-      GCONN_LAUNCHED("k_finish_segs");
+      const uint32_t grid = persistent_grid(k_finish<R, OffT>, block);
+      k_finish<R, OffT><<<grid, block, 0, s>>>(off, g.nbrs, wl, ctrl, link_ctx());
+      GCONN_LAUNCHED("k_finish");
       return GCONN_OK;
     });
   }
@@ -1049,12 +1462,9 @@ struct Run {
   template <typename OffT>
   gconn_status materialize(uint32_t* esrc, uint32_t* edst) {
     const OffT* off = static_cast<const OffT*>(g.offsets);
-    k_materialize_small<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, small, ctrl, esrc,
-                                                                  edst);
-    GCONN_LAUNCHED("k_materialize_small");
-    k_materialize_segs<OffT><<<kPersistentBlocks, block, 0, s>>>(off, g.nbrs, segs, ctrl, esrc,
-                                                                 edst);
-    GCONN_LAUNCHED("k_materialize_segs");
+    const uint32_t grid = persistent_grid(k_materialize<OffT>, block);
+    k_materialize<OffT><<<grid, block, 0, s>>>(off, g.nbrs, wl, ctrl, esrc, edst);
+    GCONN_LAUNCHED("k_materialize");
     return GCONN_OK;
   }
 
@@ -1155,8 +1565,8 @@ gconn_status launch_fill(uint32_t* p, uint32_t value, uint64_t count, hipStream_
 
 gconn_status launch_finalize(uint32_t* P, uint32_t n, uint32_t* labels, hipStream_t s) {
   if (n == 0) return GCONN_OK;
-  k_compress<<<grid_for(n, 256), 256, 0, s>>>(P, labels, n);
-  GCONN_LAUNCHED("k_compress(finalize)");
+  k_compress_to<<<grid_for(n, 256), 256, 0, s>>>(P, labels, n);
+  GCONN_LAUNCHED("k_compress_to");
   return GCONN_OK;
 }
 
@@ -1300,8 +1710,12 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
   if (forest && !labels) L.P = take(4 * n);
   const bool csr = g.format == GCONN_CSR;
   if (csr) {
-    L.small = take(4 * n);
-    L.seg_cap = m / (kSmallDeg + 1) + 1;
+    const uint64_t groups = (n + 63) / 64;
+    L.sub_cap = (uint32_t)(((groups + kSubLists - 1) / kSubLists) * 64);
+    L.small = take(4ull * kSubLists * L.sub_cap);
+    L.medium = take(4ull * kSubLists * L.sub_cap);
+    // a vertex of degree d > kMedDeg (= kSeg) yields ceil(d / kSeg) <= 2d / kSeg segments
+    L.seg_cap = 2 * m / kSeg + 1;
     L.segs = take(8 * L.seg_cap);
   }
   if (o.link == GCONN_LINK_HOOKS) L.hooks = take(4 * n);
@@ -1333,12 +1747,11 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
   const uint32_t block = run.block;
   prof_count_run();
   GCONN_TRY(prof_mark(kPhaseInit, true, s));
-  k_ctrl_init<<<1, 256, 0, s>>>(run.ctrl);
-  GCONN_LAUNCHED("k_ctrl_init");
-  if (n > 0) {
-    k_init<<<grid_for(n, block), block, 0, s>>>(P, n, fu, fv);
-    GCONN_LAUNCHED("k_init");
-  }
+  const bool vec = (reinterpret_cast<uintptr_t>(P) % 16) == 0 &&
+                   (!fu || ((reinterpret_cast<uintptr_t>(fu) | reinterpret_cast<uintptr_t>(fv)) % 16) == 0);
+  k_init<<<grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), block), block, 0, s>>>(run.ctrl, P, n, fu,
+                                                                                fv, vec ? 1 : 0);
+  GCONN_LAUNCHED("k_init");
   if (run.hooks) GCONN_TRY(launch_fill(run.hooks, kEmpty, n, s));
   GCONN_TRY(prof_mark(kPhaseInit, false, s));
 
@@ -1364,10 +1777,10 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
 
   const bool iterative =
       o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
+  const bool sampled = csr && o.sample != GCONN_SAMPLE_NONE;
   if (n > 0 && g.m > 0) {
     if (csr) {
-      if (o.sample != GCONN_SAMPLE_NONE)
-        GCONN_TRY(o64 ? run.sample_phase<uint64_t>() : run.sample_phase<uint32_t>());
+      if (sampled) GCONN_TRY(o64 ? run.sample_phase<uint64_t>() : run.sample_phase<uint32_t>());
       GCONN_TRY(prof_mark(kPhaseGather, true, s));
       GCONN_TRY(o64 ? run.gather<uint64_t>() : run.gather<uint32_t>());
       GCONN_TRY(prof_mark(kPhaseGather, false, s));
@@ -1389,10 +1802,11 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
       uint32_t* esrc = reinterpret_cast<uint32_t*>(ws + L.esrc);
       uint32_t* edst = reinterpret_cast<uint32_t*>(ws + L.edst);
       if (csr) {
-        GCONN_TRY(o64 ? run.materialize<uint64_t>(esrc, edst) : run.materialize<uint32_t>(esrc, edst));
+        GCONN_TRY(o64 ? run.materialize<uint64_t>(esrc, edst)
+                      : run.materialize<uint32_t>(esrc, edst));
       } else {
-        k_materialize_coo<<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m, run.ctrl, esrc,
-                                                                edst);
+        k_materialize_coo<<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m, run.ctrl,
+                                                                esrc, edst);
         GCONN_LAUNCHED("k_materialize_coo");
       }
       GCONN_TRY(run.iterate(esrc, edst));
@@ -1401,8 +1815,9 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
     if (finalize || o.link == GCONN_LINK_ECL) {
       // ECL-CC's separate full-compress pass doubles as finalisation.
       GCONN_TRY(prof_mark(kPhaseFinalize, true, s));
-      k_compress<<<grid_for(n, block), block, 0, s>>>(P, P, n);
-      GCONN_LAUNCHED("k_compress(finalize)");
+      const uint32_t grid = persistent_grid(k_finalize, block);
+      k_finalize<<<grid, block, 0, s>>>(P, n, run.ctrl, run.wl, (sampled && csr) ? 1 : 0);
+      GCONN_LAUNCHED("k_finalize");
       GCONN_TRY(prof_mark(kPhaseFinalize, false, s));
     }
   }

@@ -22,6 +22,7 @@ SAMPLE = {"none": 0, "kout": 1, "hb": 2, "bfs": 3}
 LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt": 6, "lp": 7}
 FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3}
 SPLICE = {"split_one": 0, "halve_one": 1}
+SCHEDULE = {"auto": 0, "lane": 1, "step": 2}
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
                "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]
 STATUS = {0: "GCONN_OK", -1: "GCONN_EINVAL", -2: "GCONN_ENOMEM", -3: "GCONN_EDEVICE",
@@ -47,7 +48,7 @@ class _Options(ctypes.Structure):
                 ("k", ctypes.c_uint32), ("hb_n", ctypes.c_uint32),
                 ("lmax_samples", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("kout_random", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -138,6 +139,7 @@ class Options:
     kout_random: bool = False
     validate: bool = False
     block: int = 256
+    schedule: str = "auto"
 
     def to_c(self) -> _Options:
         o = _Options()
@@ -152,6 +154,7 @@ class Options:
         o.kout_random = int(self.kout_random)
         o.validate = int(self.validate)
         o.block = self.block
+        o.schedule = SCHEDULE[self.schedule]
         return o
 
 

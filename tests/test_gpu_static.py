@@ -307,3 +307,51 @@ def test_incremental_validation():
     out = inc.query(torch.tensor([1, 1], dtype=torch.int32, device="cuda"),
                     torch.tensor([2, 3], dtype=torch.int32, device="cuda"))
     assert out.cpu().tolist() == [1, 0]
+
+
+def test_kout_rem_cas_schedules_agree(cases):
+    """The lane-refill step machine and the one-lane-per-vertex loop give the
+    oracle's labels, a valid forest and the oracle's sampled-edge count."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    for name, (C, dg, want) in cases.items():
+        roots_mask = want != np.arange(C.n, dtype=np.uint32)
+        for k in (1, 2, 3):
+            _, e_s = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
+            for find in ("naive", "split", "halve"):
+                for splice in ("split_one", "halve_one"):
+                    for sched in ("auto", "lane", "step"):
+                        say(f"[sched] graph={name} k={k} find={find} splice={splice} sched={sched}")
+                        o = G.Options(sample="kout", link="rem_cas", find=find, splice=splice,
+                                      k=k, schedule=sched)
+                        lab, st = G.cc(dg, options=o, stats=True)
+                        assert np.array_equal(G.to_u32(lab), want), (name, k, find, splice, sched)
+                        if C.m:
+                            assert st["sampled_edges"] == e_s
+                        fu, fv, _ = G.spanning_forest(dg, want_labels=False, options=o)
+                        torch.cuda.synchronize()
+                        fu, fv = G.to_u32(fu), G.to_u32(fv)
+                        oracle.check_forest(C.n, C.offsets, C.nbrs, fu, fv, want)
+                        assert np.array_equal(fu != G.EMPTY, roots_mask)
+
+
+def test_hooks_count_is_n_minus_c_with_sampling(cases):
+    from paper_2008_11839_amd import gconn as G
+    for name, (C, dg, want) in cases.items():
+        c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
+        for sched in ("auto", "lane", "step"):
+            lab, st = G.cc(dg, options=G.Options(sample="kout", link="rem_cas", schedule=sched),
+                           stats=True)
+            assert st["hooks"] == C.n - c, (name, sched)
+
+
+def test_random_kout_and_larger_k(cases):
+    from paper_2008_11839_amd import gconn as G
+    for name, (C, dg, want) in cases.items():
+        for k in (1, 2, 3, 5):
+            for random in (False, True):
+                for link in ("async", "rem_cas", "early"):
+                    for sched in ("auto", "lane"):
+                        got = _labels(G, dg, sample="kout", k=k, kout_random=random, link=link,
+                                      schedule=sched, seed=7)
+                        assert np.array_equal(got, want), (name, k, random, link, sched)
