@@ -198,6 +198,61 @@ gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream);
 /* Frees the host handle only (no device memory is owned). */
 gconn_status gconn_inc_destroy(gconn_inc* h);
 
+/* ------------------------------------------------------------- many graphs
+ * Many independent graphs connected by one pipeline run (one launch per phase
+ * for all of them).  Graph g owns the vertex range [vbase[g], vbase[g+1]) of
+ * one concatenated CSR whose neighbour ids are global (vbase[g] + local id);
+ * its edges must stay inside its range.  Every vbase[g] is a multiple of 64
+ * (pad with isolated vertices), so each 64-vertex tile belongs to one graph.
+ * Each graph gets its own L_max (the paper's sampling/finish split, per
+ * graph), and each graph class its own sampling and union-find rule, chosen
+ * per class by a caller or by gconn_autotune and dispatched inside the same
+ * kernels. */
+#define GCONN_MAX_CLASSES 64
+
+typedef struct gconn_batch {
+  uint32_t num_graphs;         /* G                                                */
+  uint32_t n;                  /* vbase[G]: all vertices, padding included         */
+  uint64_t m;                  /* total CSR entries                                */
+  const uint64_t* offsets;     /* device, n + 1 (global)                           */
+  const uint32_t* nbrs;        /* device, m global neighbour ids                   */
+  const uint32_t* vbase;       /* device, G + 1: vbase[0] = 0, multiples of 64     */
+  const uint8_t* graph_class;  /* device, G class indices (NULL: every graph in 0) */
+} gconn_batch;
+
+typedef struct gconn_class_options {
+  int32_t sample;    /* GCONN_SAMPLE_NONE or GCONN_SAMPLE_KOUT (first k edges)      */
+  int32_t link;      /* GCONN_LINK_ASYNC, GCONN_LINK_REM_CAS or GCONN_LINK_EARLY    */
+  int32_t find;      /* GCONN_FIND_NAIVE, _SPLIT or _HALVE                          */
+  int32_t splice;    /* GCONN_SPLICE_* (Union-Rem-CAS)                              */
+  uint32_t k;        /* k-out edges per vertex (1..64)                              */
+  uint32_t reserved;
+} gconn_class_options;
+
+gconn_status gconn_cc_batch_workspace_size(const gconn_batch* b, size_t* bytes);
+
+/* labels_out (device, n entries, caller-owned) receives, for every vertex v of
+ * graph g, the minimum LOCAL id (id - vbase[g]) of v's component in graph g;
+ * padding vertices get their own local id.  classes: host array of
+ * num_classes (1..GCONN_MAX_CLASSES) entries.  lmax_samples / seed: as in
+ * gconn_options.  Asynchronous on `stream` (synchronous if stats != NULL). */
+gconn_status gconn_cc_batch(const gconn_batch* b, uint32_t* labels_out, void* workspace,
+                            size_t workspace_bytes, const gconn_class_options* classes,
+                            uint32_t num_classes, uint32_t lmax_samples, uint64_t seed,
+                            gconn_stats* stats, void* stream);
+
+/* Autotuner step: times every candidate option set on every given graph
+ * (one warm-up, then `reps` timed runs each, HIP events on `stream`) and
+ * writes the index of the candidate with the smallest total to *best and the
+ * totals (ms) to times_ms (host, num_candidates entries, nullable).
+ * labels_scratch: device, at least max n entries.  workspace: device, large
+ * enough for every candidate on every graph.  Synchronous. */
+gconn_status gconn_autotune(const gconn_graph* graphs, uint32_t num_graphs,
+                            const gconn_options* candidates, uint32_t num_candidates,
+                            uint32_t reps, uint32_t* labels_scratch, void* workspace,
+                            size_t workspace_bytes, void* stream, uint32_t* best,
+                            double* times_ms);
+
 /* Per-phase device time of the static pipeline (gconn_cc, gconn_spanning_forest,
  * the initial graph of gconn_inc_create).  While profiling is enabled on the
  * calling thread, each phase is bracketed by HIP events recorded on the call's

@@ -317,6 +317,30 @@ gconn_status gconn_inc_destroy(gconn_inc* h) {
   return GCONN_OK;
 }
 
+gconn_status gconn_cc_batch_workspace_size(const gconn_batch* b, size_t* bytes) {
+  clear_error();
+  return batch_workspace_size(b, bytes);
+}
+
+gconn_status gconn_cc_batch(const gconn_batch* b, uint32_t* labels_out, void* workspace,
+                            size_t workspace_bytes, const gconn_class_options* classes,
+                            uint32_t num_classes, uint32_t lmax_samples, uint64_t seed,
+                            gconn_stats* stats, void* stream) {
+  clear_error();
+  return run_batch(b, labels_out, workspace, workspace_bytes, classes, num_classes, lmax_samples,
+                   seed, stats, static_cast<hipStream_t>(stream));
+}
+
+gconn_status gconn_autotune(const gconn_graph* graphs, uint32_t num_graphs,
+                            const gconn_options* candidates, uint32_t num_candidates,
+                            uint32_t reps, uint32_t* labels_scratch, void* workspace,
+                            size_t workspace_bytes, void* stream, uint32_t* best,
+                            double* times_ms) {
+  clear_error();
+  return autotune(graphs, num_graphs, candidates, num_candidates, reps, labels_scratch, workspace,
+                  workspace_bytes, static_cast<hipStream_t>(stream), best, times_ms);
+}
+
 gconn_status gconn_profile_enable(int on) { return profile_enable(on); }
 
 gconn_status gconn_profile_read(gconn_phase_times* out, int reset) {

@@ -118,6 +118,18 @@ gconn_status launch_fill(uint32_t* p, uint32_t value, uint64_t count, hipStream_
 gconn_status launch_finalize(uint32_t* P, uint32_t n, uint32_t* labels, hipStream_t s);
 gconn_status launch_insert(const gconn_options& o, uint32_t* P, uint32_t* H, const uint32_t* src,
                            const uint32_t* dst, uint64_t k, hipStream_t s);
+// Clear the control block and set P[v] = v (one kernel).
+gconn_status reset_ctrl_and_parents(Ctrl* ctrl, uint32_t* P, uint32_t n, hipStream_t s);
+// Many-graph pipeline and autotuner step (gconn_batch.hip).
+gconn_status batch_workspace_size(const gconn_batch* b, size_t* bytes);
+gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspace,
+                       size_t workspace_bytes, const gconn_class_options* classes,
+                       uint32_t num_classes, uint32_t lmax_samples, uint64_t seed,
+                       gconn_stats* stats, hipStream_t s);
+gconn_status autotune(const gconn_graph* graphs, uint32_t num_graphs,
+                      const gconn_options* candidates, uint32_t num_candidates, uint32_t reps,
+                      uint32_t* labels_scratch, void* workspace, size_t workspace_bytes,
+                      hipStream_t s, uint32_t* best, double* times_ms);
 // Synchronous id check of a pair list (ids < n); uses ctrl as scratch.
 gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, uint32_t n,
                             Ctrl* ctrl, hipStream_t s);

@@ -58,6 +58,17 @@ class _Stats(ctypes.Structure):
                 ("bfs_source", ctypes.c_uint32)]
 
 
+class _Batch(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_uint32), ("n", ctypes.c_uint32), ("m", ctypes.c_uint64),
+                ("offsets", ctypes.c_void_p), ("nbrs", ctypes.c_void_p), ("vbase", ctypes.c_void_p),
+                ("graph_class", ctypes.c_void_p)]
+
+
+class _ClassOptions(ctypes.Structure):
+    _fields_ = [("sample", ctypes.c_int32), ("link", ctypes.c_int32), ("find", ctypes.c_int32),
+                ("splice", ctypes.c_int32), ("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class _PhaseTimes(ctypes.Structure):
     _fields_ = [("init_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
                 ("compress_ms", ctypes.c_double), ("lmax_ms", ctypes.c_double),
@@ -65,7 +76,8 @@ class _PhaseTimes(ctypes.Structure):
                 ("finalize_ms", ctypes.c_double), ("runs", ctypes.c_uint64)]
 
 
-EXPORTS = ["gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
+EXPORTS = ["gconn_cc_batch_workspace_size", "gconn_cc_batch", "gconn_autotune",
+           "gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
            "gconn_inc_query_batch", "gconn_inc_labels", "gconn_inc_destroy",
            "gconn_status_string", "gconn_last_error", "gconn_version"]
@@ -104,6 +116,16 @@ def lib() -> ctypes.CDLL:
         L.gconn_inc_labels.argtypes = [vp, vp, vp]
         L.gconn_inc_destroy.restype = ctypes.c_int
         L.gconn_inc_destroy.argtypes = [vp]
+        bp, cp = ctypes.POINTER(_Batch), ctypes.POINTER(_ClassOptions)
+        L.gconn_cc_batch_workspace_size.restype = ctypes.c_int
+        L.gconn_cc_batch_workspace_size.argtypes = [bp, ctypes.POINTER(sz)]
+        L.gconn_cc_batch.restype = ctypes.c_int
+        L.gconn_cc_batch.argtypes = [bp, vp, vp, sz, cp, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint64, stp, vp]
+        L.gconn_autotune.restype = ctypes.c_int
+        L.gconn_autotune.argtypes = [gp, ctypes.c_uint32, op, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                     vp, sz, vp, ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.POINTER(ctypes.c_double)]
         L.gconn_profile_enable.restype = ctypes.c_int
         L.gconn_profile_enable.argtypes = [ctypes.c_int]
         L.gconn_profile_read.restype = ctypes.c_int
