@@ -74,6 +74,134 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def serving_bench(G, src, dst, n, args) -> dict:
+    """Incremental serving: the graph's edge stream as insert batches of
+    log-uniform size in [1e4, 1e7] interleaved (coin flip) with query batches
+    of 1e5 uniform pairs, fed from host memory through gconn_server.  First
+    all requests at once (saturated throughput), then Poisson arrivals at 50%
+    and 80% of that rate; latency = submission -> answers on the host."""
+    import threading
+
+    import numpy as np
+
+    import graphgen
+    rng = np.random.default_rng(args.seed)
+    reqs, e = [], 0
+    while e < len(src):
+        if rng.random() < 0.5:
+            k = int(10 ** rng.uniform(4, 7))
+            reqs.append((0, src[e:e + k], dst[e:e + k]))
+            e += k
+        else:
+            a, b = graphgen.uniform_pairs(n, 100_000, args.seed, len(reqs))
+            reqs.append((1, a, b))
+        if args.serve_requests and len(reqs) >= args.serve_requests:
+            break
+    updates = sum(len(a) for k, a, _ in reqs if k == 0)
+    queries = sum(len(a) for k, a, _ in reqs if k == 1)
+    opts = G.Options(sample="none", link="async", find="split")
+
+    def run(rate):
+        srv = G.Server(n, streams=4, arena_bytes=512 << 20, options=opts)
+        tickets = []
+        t0 = time.perf_counter()
+        if rate is None:
+            tickets = [srv.submit(k, a, b) for k, a, b in reqs]
+        else:
+            gaps = rng.exponential(1.0 / rate, size=len(reqs))
+            nxt = time.perf_counter()
+            for (k, a, b), g in zip(reqs, gaps):
+                nxt += g
+                while time.perf_counter() < nxt:
+                    pass
+                tickets.append(srv.submit(k, a, b))
+        recs = [srv.wait(t)[0] for t in tickets]
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = [(r["done_us"] - r["submit_us"]) / 1e3 for r in recs]
+        return wall, lat, recs
+
+    wall, lat, recs = run(None)
+    sat_rate = len(reqs) / wall
+    out = {"workload": f"RMAT-{args.scale} edge stream ({updates} updates in {sum(1 for r in reqs if r[0] == 0)} "
+                       f"insert batches, log-uniform 1e4..1e7) + {sum(1 for r in reqs if r[0] == 1)} "
+                       "query batches of 1e5 pairs, host-fed, 4 streams, 512 MB arena",
+           "saturated": {"updates_per_s": round(updates / wall, 1),
+                         "requests_per_s": round(sat_rate, 2), "wall_s": round(wall, 3),
+                         "latency_ms_p50": round(percentile(lat, 50), 3),
+                         "latency_ms_p99": round(percentile(lat, 99), 3)}}
+    for rho in (0.5, 0.8):
+        wall, lat, recs = run(rho * sat_rate)
+        out[f"load_{rho}"] = {"updates_per_s": round(updates / wall, 1),
+                              "latency_ms_p50": round(percentile(lat, 50), 3),
+                              "latency_ms_p99": round(percentile(lat, 99), 3)}
+    out["queries"] = queries
+    return out
+
+
+def batched_bench(G, args) -> dict:
+    """Many graphs: one gconn_cc_batch (per-class options from the autotuner)
+    against one gconn_cc launch sequence per graph, on the same device; the
+    two must give identical labels."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    from paper_2008_11839_amd import batch as B
+    t0 = time.time()
+    specs = graphgen.batched_specs(args.batch_graphs, args.seed, n_lo=1e3, n_hi=args.batch_nmax)
+    graphs = [graphgen.batched_graph(*sp) for sp in specs]
+    total_n = sum(g.n for g in graphs)
+    total_m = sum(g.m for g in graphs)
+    log(f"batched workload: {len(graphs)} graphs, n={total_n} m={total_m} ({time.time() - t0:.1f}s)")
+    tuner = B.Autotuner(reps=2, per_class=2)
+    keys = tuner.tune(graphs)
+    classes, gclass = tuner.classes_for(keys)
+    hb = B.concat(graphs)
+    db = B.upload(hb, graph_class=gclass)
+    ws_b = torch.empty(0)
+    import ctypes
+    bb = ctypes.c_size_t()
+    G._check(G.lib().gconn_cc_batch_workspace_size(ctypes.byref(db.c), ctypes.byref(bb)))
+    ws_b = G.alloc_workspace(bb.value)
+    lab_b = torch.empty(hb.n, dtype=torch.int32, device="cuda")
+    # one launch sequence per graph: each graph resident with local ids
+    dgs = [G.csr(g.offsets, g.nbrs, g.n) for g in graphs]
+    opt1 = G.Options(sample="kout", link="rem_cas", find="split")
+    need = max(G.workspace_size(d, opt1) for d in dgs)
+    ws_1 = G.alloc_workspace(need)
+    labs = [torch.empty(d.n, dtype=torch.int32, device="cuda") for d in dgs]
+    for _ in range(2):
+        B.cc_batch(db, classes, labels=lab_b, workspace=ws_b)
+        for d, l in zip(dgs, labs):
+            G.cc(d, labels=l, options=opt1, workspace=ws_1)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.cc_batch(db, classes, labels=lab_b, workspace=ws_b)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for d, l in zip(dgs, labs):
+            G.cc(d, labels=l, options=opt1, workspace=ws_1)
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / reps
+    lb = lab_b.cpu().numpy().view(np.uint32)
+    same = all(np.array_equal(lb[int(hb.vbase[i]):int(hb.vbase[i]) + g.n], G.to_u32(l))
+               for i, (g, l) in enumerate(zip(graphs, labs)))
+    return {"workload": f"{len(graphs)} graphs, n log-uniform in [1e3, {args.batch_nmax:.0e}], "
+                        "ER or RMAT by coin flip, edge factor 8..32",
+            "graphs": len(graphs), "n": total_n, "m_directed": total_m,
+            "classes": {k: tuner.table[k]["choice"] for k in sorted(set(keys))},
+            "batched_ms": round(t_batch * 1e3, 3), "per_graph_launches_ms": round(t_loop * 1e3, 3),
+            "speedup": round(t_loop / t_batch, 2),
+            "batched_gedges_per_s": round(total_m / t_batch / 1e9, 2),
+            "per_graph_gedges_per_s": round(total_m / t_loop / 1e9, 2),
+            "labels_identical": bool(same)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +219,13 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the spanning-forest and incremental measurements")
     ap.add_argument("--inc-batch", type=int, default=1_000_000)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=2000)
+    ap.add_argument("--batch-nmax", type=float, default=1e5,
+                    help="largest graph of the many-graph batch (the full workload uses 1e6)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="cap on served requests (0: the whole edge stream)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -286,6 +421,16 @@ def main() -> int:
         }
         log(f"incremental {result['incremental']}")
         del s_in, d_in
+
+    # ------------------------------------------------------------ serving loop (host-fed)
+    if not args.no_extras and not args.no_serving:
+        result["serving"] = serving_bench(G, src, dst, n, args)
+        log(f"serving {result['serving']}")
+
+    # ------------------------------------------------------------ many-graph batch
+    if not args.no_extras and not args.no_batched:
+        result["batched"] = batched_bench(G, args)
+        log(f"batched {result['batched']}")
 
     # ------------------------------------------------------------ CPU oracle baseline
     if not args.no_cpu_baseline:

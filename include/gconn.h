@@ -253,6 +253,62 @@ gconn_status gconn_autotune(const gconn_graph* graphs, uint32_t num_graphs,
                             size_t workspace_bytes, void* stream, uint32_t* best,
                             double* times_ms);
 
+/* ------------------------------------------------------------- serving
+ * A request loop over one resident parent array (incremental connectivity
+ * served online).  Clients submit insert or query batches from host memory
+ * at any time; a worker thread admits them in submission order while the
+ * caller's device arena (and a pinned host staging area of the same size the
+ * server allocates) has room for their data -- admission by HBM footprint --
+ * copies them to the device and runs them on several HIP streams.  Requests of
+ * the same kind that follow each other form an epoch and overlap on the device
+ * (inserts commute; queries only read connectivity); the first request of a
+ * new epoch, and every request after it in that epoch, waits on events
+ * recorded on every stream when the epoch began, so a query batch sees exactly
+ * the inserts submitted before it and no later one.  Each request's answers
+ * are therefore the same whether it runs alone or in a mix.  The server's
+ * streams have default priority. */
+typedef struct gconn_server gconn_server;
+
+enum { GCONN_REQ_INSERT = 0, GCONN_REQ_QUERY = 1 };
+
+typedef struct gconn_server_config {
+  uint32_t n_max;          /* vertices (ids < n_max)                                */
+  uint32_t streams;        /* device streams for overlap, 1..16 (0 -> 4)            */
+  uint64_t arena_bytes;    /* device arena = in-flight budget; insert of k edges
+                              needs 8k bytes, query of q pairs 9q (each rounded up
+                              to 256)                                                */
+  gconn_options options;   /* union-find rule for inserts, find rule for queries   */
+} gconn_server_config;
+
+typedef struct gconn_request_info {
+  int32_t kind;            /* GCONN_REQ_*                                           */
+  int32_t status;          /* gconn_status of the request                           */
+  uint64_t count;          /* edges or pairs                                        */
+  uint64_t epoch;          /* epoch number it ran in                                */
+  double submit_us;        /* microseconds since server creation                    */
+  double admit_us;
+  double done_us;          /* result visible on the host                            */
+} gconn_request_info;
+
+/* parent_buf: device, n_max entries; arena: device, arena_bytes; both
+ * caller-owned and kept until gconn_server_destroy.  The parent array is
+ * initialised here (P[v] = v). */
+gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* parent_buf,
+                                 void* arena, gconn_server** out);
+/* Copies nothing yet: a, b (host, count entries) and out (host, count bytes,
+ * queries only: 1 iff connected) must stay valid until the request is done.
+ * Returns GCONN_EINVAL for a request larger than the arena.  Thread-safe. */
+gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, const uint32_t* b,
+                                 uint64_t count, uint8_t* out, uint64_t* ticket);
+/* Blocks until the request is done or timeout_s (< 0: no limit) elapses
+ * (GCONN_ETIMEOUT).  info (nullable) receives its record. */
+gconn_status gconn_server_wait(gconn_server* s, uint64_t ticket, double timeout_s,
+                               gconn_request_info* info);
+/* Blocks until every submitted request is done. */
+gconn_status gconn_server_drain(gconn_server* s);
+/* Drains, stops the worker, frees host resources (not the caller's buffers). */
+gconn_status gconn_server_destroy(gconn_server* s);
+
 /* Per-phase device time of the static pipeline (gconn_cc, gconn_spanning_forest,
  * the initial graph of gconn_inc_create).  While profiling is enabled on the
  * calling thread, each phase is bracketed by HIP events recorded on the call's

@@ -1,0 +1,358 @@
+// gconn_server.hip -- continuous-batching request loop for incremental
+// connectivity (gconn_server_* in include/gconn.h).  Host code only: the
+// device work is the incremental insert / query kernels of gconn_static.hip.
+//
+// One worker thread owns every HIP call after creation.  Its loop:
+//   1. admit pending requests in submission order while the device arena and
+//      the pinned staging area have room (first-fit allocator, 256-byte
+//      granules); a request that does not fit stops admission until earlier
+//      requests complete and free space;
+//   2. on admission: copy the request's host data into pinned staging, pick the
+//      next stream round-robin; if its kind differs from the current epoch's,
+//      open a new epoch by recording one fence event on every stream; make the
+//      stream wait on the current epoch's fences; enqueue H2D copy, kernel,
+//      (queries) D2H of the answers, and a completion event;
+//   3. poll completion events; for finished queries copy the answers from
+//      staging into the caller's buffer; free the arena space; publish the
+//      request record and wake waiters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gconn_internal.hpp"
+
+namespace gconn {
+namespace {
+
+constexpr uint64_t kGranule = 256;
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class RangeAlloc {
+ public:
+  explicit RangeAlloc(uint64_t size) { if (size) free_[0] = size; }
+  bool alloc(uint64_t bytes, uint64_t* at) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        *at = it->first;
+        const uint64_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        return true;
+      }
+    return false;
+  }
+  void release(uint64_t at, uint64_t bytes) {
+    auto it = free_.emplace(at, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+ private:
+  std::map<uint64_t, uint64_t> free_;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  int kind = 0;
+  const uint32_t* a = nullptr;
+  const uint32_t* b = nullptr;
+  uint8_t* out = nullptr;
+  uint64_t count = 0;
+  uint64_t bytes = 0;     // arena / staging footprint
+  uint64_t at = 0;        // offset in the arena and staging area
+  int stream = 0;
+  hipEvent_t done = nullptr;
+  gconn_request_info info{};
+};
+
+uint64_t footprint(int kind, uint64_t count) {
+  const uint64_t raw = kind == GCONN_REQ_INSERT ? 8 * count : 9 * count;
+  return align_up(raw ? raw : 1, kGranule);
+}
+
+}  // namespace
+}  // namespace gconn
+
+using namespace gconn;
+
+struct gconn_server {
+  gconn_server_config cfg{};
+  uint32_t* P = nullptr;
+  uint8_t* arena = nullptr;
+  uint8_t* staging = nullptr;  // pinned host, same size as the arena
+  int device = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> fences;
+  std::vector<hipEvent_t> event_pool;
+  RangeAlloc space{0};
+  std::chrono::steady_clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::unique_ptr<Request>> pending;  // submitted, not admitted
+  std::vector<std::unique_ptr<Request>> inflight;
+  std::unordered_map<uint64_t, gconn_request_info> finished;
+  uint64_t next_ticket = 1;
+  uint64_t submitted = 0, completed = 0;
+  bool stop = false;
+  std::thread worker;
+
+  int epoch_kind = -1;
+  uint64_t epoch = 0;
+  int rr = 0;
+
+  double now_us() const {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+
+  // Enqueue one admitted request on its stream (worker thread, HIP device set).
+  gconn_status launch(Request& r) {
+    hipStream_t s = streams[r.stream];
+    if (r.kind != epoch_kind) {
+      // new epoch: fence everything already enqueued on every stream
+      for (size_t t = 0; t < streams.size(); ++t)
+        GCONN_HIP(hipEventRecord(fences[t], streams[t]));
+      epoch_kind = r.kind;
+      ++epoch;
+    }
+    r.info.epoch = epoch;
+    // The fences of the current epoch order this request after every earlier
+    // epoch; waiting on a fence that is older than the stream's own work is a
+    // no-op for correctness.
+    if (epoch > 1)
+      for (size_t t = 0; t < streams.size(); ++t) GCONN_HIP(hipStreamWaitEvent(s, fences[t], 0));
+    uint8_t* dev = arena + r.at;
+    uint8_t* host = staging + r.at;
+    uint32_t* da = reinterpret_cast<uint32_t*>(dev);
+    uint32_t* db = da + r.count;
+    std::memcpy(host, r.a, 4 * r.count);
+    std::memcpy(host + 4 * r.count, r.b, 4 * r.count);
+    GCONN_HIP(hipMemcpyAsync(dev, host, 8 * r.count, hipMemcpyHostToDevice, s));
+    if (r.kind == GCONN_REQ_INSERT) {
+      uint32_t* H = nullptr;  // Union-Hooks is not offered by the server
+      GCONN_TRY(launch_insert(cfg.options, P, H, da, db, r.count, s));
+    } else {
+      uint8_t* dout = dev + 8 * r.count;
+      GCONN_TRY(launch_query(cfg.options, P, da, db, r.count, dout, s));
+      GCONN_HIP(hipMemcpyAsync(host + 8 * r.count, dout, r.count, hipMemcpyDeviceToHost, s));
+    }
+    r.done = get_event();
+    if (!r.done) return fail(GCONN_EDEVICE, "hipEventCreate failed");
+    GCONN_HIP(hipEventRecord(r.done, s));
+    return GCONN_OK;
+  }
+
+  void finish_request(std::unique_ptr<Request>& r, gconn_status st) {
+    if (st == GCONN_OK && r->kind == GCONN_REQ_QUERY && r->out)
+      std::memcpy(r->out, staging + r->at + 8 * r->count, r->count);
+    space.release(r->at, r->bytes);
+    if (r->done) event_pool.push_back(r->done);
+    r->info.status = st;
+    r->info.done_us = now_us();
+    std::lock_guard<std::mutex> lock(mu);
+    finished[r->ticket] = r->info;
+    ++completed;
+    cv_done.notify_all();
+  }
+
+  void run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+      // 1. admission, in submission order
+      for (;;) {
+        std::unique_ptr<Request> r;
+        {
+          std::lock_guard<std::mutex> lock(mu);
+          if (pending.empty()) break;
+          uint64_t at = 0;
+          if (!space.alloc(pending.front()->bytes, &at)) break;  // wait for space
+          r = std::move(pending.front());
+          pending.pop_front();
+          r->at = at;
+        }
+        r->stream = rr;
+        rr = (rr + 1) % (int)streams.size();
+        r->info.admit_us = now_us();
+        const gconn_status st = launch(*r);
+        if (st != GCONN_OK) {
+          finish_request(r, st);
+          continue;
+        }
+        inflight.push_back(std::move(r));
+      }
+      // 2. completions
+      bool progressed = false;
+      for (size_t i = 0; i < inflight.size();) {
+        const hipError_t q = hipEventQuery(inflight[i]->done);
+        if (q == hipErrorNotReady) {
+          ++i;
+          continue;
+        }
+        const gconn_status st = q == hipSuccess ? GCONN_OK : hip_fail(q, "request");
+        finish_request(inflight[i], st);
+        inflight[i] = std::move(inflight.back());
+        inflight.pop_back();
+        progressed = true;
+      }
+      // 3. sleep when idle
+      std::unique_lock<std::mutex> lock(mu);
+      if (stop && pending.empty() && inflight.empty()) break;
+      if (!progressed && inflight.empty() && pending.empty())
+        cv_work.wait_for(lock, std::chrono::milliseconds(5));
+      else if (!progressed)
+        cv_work.wait_for(lock, std::chrono::microseconds(20));
+    }
+  }
+};
+
+extern "C" {
+
+gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* parent_buf, void* arena,
+                                 gconn_server** out) {
+  clear_error();
+  if (!cfg || !out) return fail(GCONN_EINVAL, "cfg and out are required");
+  *out = nullptr;
+  GCONN_TRY(check_options(cfg->options));
+  if (!is_union_find(cfg->options.link) || cfg->options.link == GCONN_LINK_HOOKS)
+    return fail(GCONN_EUNSUPPORTED,
+                "the server runs Union-Async, Union-Early, Union-Rem-CAS or ECL-CC's rule");
+  if (cfg->n_max == 0 || cfg->n_max > 0xFFFFFFFEu) return fail(GCONN_EINVAL, "n_max out of range");
+  if (cfg->streams > 16) return fail(GCONN_EINVAL, "streams must be 1..16");
+  if (cfg->arena_bytes < kGranule) return fail(GCONN_EINVAL, "arena too small");
+  GCONN_TRY(check_device_ready());
+  GCONN_TRY(check_device_ptr(parent_buf, "parent_buf"));
+  GCONN_TRY(check_device_ptr(arena, "arena"));
+  if (reinterpret_cast<uintptr_t>(arena) % kGranule != 0)
+    return fail(GCONN_EINVAL, "arena must be 256-byte aligned");
+  std::unique_ptr<gconn_server> s(new (std::nothrow) gconn_server);
+  if (!s) return fail(GCONN_EINVAL, "host allocation failed");
+  s->cfg = *cfg;
+  if (s->cfg.streams == 0) s->cfg.streams = 4;
+  s->P = parent_buf;
+  s->arena = static_cast<uint8_t*>(arena);
+  s->space = RangeAlloc(cfg->arena_bytes / kGranule * kGranule);
+  GCONN_HIP(hipGetDevice(&s->device));
+  GCONN_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->staging), cfg->arena_bytes,
+                          hipHostMallocDefault));
+  for (uint32_t t = 0; t < s->cfg.streams; ++t) {
+    hipStream_t st = nullptr;
+    GCONN_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    s->streams.push_back(st);
+    hipEvent_t e = nullptr;
+    GCONN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    s->fences.push_back(e);
+  }
+  GCONN_TRY(launch_iota(parent_buf, cfg->n_max, s->streams[0]));
+  GCONN_HIP(hipStreamSynchronize(s->streams[0]));
+  s->t0 = std::chrono::steady_clock::now();
+  gconn_server* raw = s.release();
+  raw->worker = std::thread([raw] { raw->run(); });
+  *out = raw;
+  return GCONN_OK;
+}
+
+gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, const uint32_t* b,
+                                 uint64_t count, uint8_t* out, uint64_t* ticket) {
+  if (!s || !ticket) return fail(GCONN_EINVAL, "server and ticket are required");
+  if (kind != GCONN_REQ_INSERT && kind != GCONN_REQ_QUERY)
+    return fail(GCONN_EINVAL, "kind must be GCONN_REQ_INSERT or GCONN_REQ_QUERY");
+  if (count > 0 && (!a || !b)) return fail(GCONN_EINVAL, "a and b are required");
+  if (kind == GCONN_REQ_QUERY && count > 0 && !out) return fail(GCONN_EINVAL, "out is required");
+  auto r = std::make_unique<Request>();
+  r->kind = kind;
+  r->a = a;
+  r->b = b;
+  r->out = out;
+  r->count = count;
+  r->bytes = footprint(kind, count);
+  if (r->bytes > s->cfg.arena_bytes)
+    return fail(GCONN_EINVAL, "request larger than the server arena");
+  r->info.kind = kind;
+  r->info.count = count;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (s->stop) return fail(GCONN_EBUSY, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    r->info.submit_us = s->now_us();
+    *ticket = r->ticket;
+    s->pending.push_back(std::move(r));
+    ++s->submitted;
+  }
+  s->cv_work.notify_one();
+  return GCONN_OK;
+}
+
+gconn_status gconn_server_wait(gconn_server* s, uint64_t ticket, double timeout_s,
+                               gconn_request_info* info) {
+  if (!s) return fail(GCONN_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lock(s->mu);
+  if (ticket == 0 || ticket >= s->next_ticket) return fail(GCONN_EINVAL, "unknown ticket");
+  auto ready = [&] { return s->finished.count(ticket) != 0; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lock, ready);
+  } else if (!s->cv_done.wait_for(lock, std::chrono::duration<double>(timeout_s), ready)) {
+    return fail(GCONN_ETIMEOUT, "request not done within the timeout");
+  }
+  const gconn_request_info rec = s->finished[ticket];
+  if (info) *info = rec;
+  return (gconn_status)rec.status;
+}
+
+gconn_status gconn_server_drain(gconn_server* s) {
+  if (!s) return fail(GCONN_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lock(s->mu);
+  s->cv_done.wait(lock, [&] { return s->completed == s->submitted; });
+  return GCONN_OK;
+}
+
+gconn_status gconn_server_destroy(gconn_server* s) {
+  if (!s) return GCONN_OK;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  for (auto e : s->fences) (void)hipEventDestroy(e);
+  for (auto e : s->event_pool) (void)hipEventDestroy(e);
+  if (s->staging) (void)hipHostFree(s->staging);
+  delete s;
+  return GCONN_OK;
+}
+
+}  // extern "C"

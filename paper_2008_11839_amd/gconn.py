@@ -69,6 +69,17 @@ class _ClassOptions(ctypes.Structure):
                 ("splice", ctypes.c_int32), ("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("arena_bytes", ctypes.c_uint64), ("options", _Options)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("status", ctypes.c_int32), ("count", ctypes.c_uint64),
+                ("epoch", ctypes.c_uint64), ("submit_us", ctypes.c_double),
+                ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
 class _PhaseTimes(ctypes.Structure):
     _fields_ = [("init_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
                 ("compress_ms", ctypes.c_double), ("lmax_ms", ctypes.c_double),
@@ -76,7 +87,8 @@ class _PhaseTimes(ctypes.Structure):
                 ("finalize_ms", ctypes.c_double), ("runs", ctypes.c_uint64)]
 
 
-EXPORTS = ["gconn_cc_batch_workspace_size", "gconn_cc_batch", "gconn_autotune",
+EXPORTS = ["gconn_server_create", "gconn_server_submit", "gconn_server_wait",
+           "gconn_server_drain", "gconn_server_destroy", "gconn_cc_batch_workspace_size", "gconn_cc_batch", "gconn_autotune",
            "gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
            "gconn_inc_query_batch", "gconn_inc_labels", "gconn_inc_destroy",
@@ -126,6 +138,18 @@ def lib() -> ctypes.CDLL:
         L.gconn_autotune.argtypes = [gp, ctypes.c_uint32, op, ctypes.c_uint32, ctypes.c_uint32, vp,
                                      vp, sz, vp, ctypes.POINTER(ctypes.c_uint32),
                                      ctypes.POINTER(ctypes.c_double)]
+        L.gconn_server_create.restype = ctypes.c_int
+        L.gconn_server_create.argtypes = [ctypes.POINTER(_ServerConfig), vp, vp, ctypes.POINTER(vp)]
+        L.gconn_server_submit.restype = ctypes.c_int
+        L.gconn_server_submit.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_uint64, vp,
+                                          ctypes.POINTER(ctypes.c_uint64)]
+        L.gconn_server_wait.restype = ctypes.c_int
+        L.gconn_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double,
+                                        ctypes.POINTER(_RequestInfo)]
+        L.gconn_server_drain.restype = ctypes.c_int
+        L.gconn_server_drain.argtypes = [vp]
+        L.gconn_server_destroy.restype = ctypes.c_int
+        L.gconn_server_destroy.argtypes = [vp]
         L.gconn_profile_enable.restype = ctypes.c_int
         L.gconn_profile_enable.argtypes = [ctypes.c_int]
         L.gconn_profile_read.restype = ctypes.c_int
@@ -357,6 +381,63 @@ def profile_read(reset: bool = True) -> dict:
     t = _PhaseTimes()
     _check(lib().gconn_profile_read(ctypes.byref(t), int(reset)))
     return {f: getattr(t, f) for f, _ in _PhaseTimes._fields_}
+
+
+INSERT, QUERY = 0, 1
+
+
+class Server:
+    """Handle over gconn_server_*: a continuous-batching request loop over one
+    resident parent array.  submit() takes host numpy arrays (kept referenced
+    here until waited on); wait() returns the request record and, for queries,
+    the answers."""
+
+    def __init__(self, n_max: int, streams: int = 4, arena_bytes: int = 64 << 20,
+                 options: Options | None = None, device="cuda"):
+        cfg = _ServerConfig()
+        cfg.n_max, cfg.streams, cfg.arena_bytes = n_max, streams, arena_bytes
+        cfg.options = (options or Options(sample="none")).to_c()
+        self.parent = torch.empty(n_max, dtype=torch.int32, device=device)
+        self.arena = alloc_workspace(arena_bytes, device)
+        h = ctypes.c_void_p()
+        _check(lib().gconn_server_create(ctypes.byref(cfg), self.parent.data_ptr(),
+                                         self.arena.data_ptr(), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, kind: int, a: np.ndarray, b: np.ndarray) -> int:
+        a = np.ascontiguousarray(a, dtype=np.uint32)
+        b = np.ascontiguousarray(b, dtype=np.uint32)
+        out = np.zeros(len(a), np.uint8) if kind == QUERY else None
+        t = ctypes.c_uint64()
+        _check(lib().gconn_server_submit(self._h, kind, a.ctypes.data if len(a) else None,
+                                         b.ctypes.data if len(b) else None, len(a),
+                                         out.ctypes.data if out is not None and len(a) else None,
+                                         ctypes.byref(t)))
+        self._keep[t.value] = (a, b, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        info = _RequestInfo()
+        st = lib().gconn_server_wait(self._h, ticket, timeout, ctypes.byref(info))
+        _check(st)
+        a, b, out = self._keep.pop(ticket)
+        rec = {f: getattr(info, f) for f, _ in _RequestInfo._fields_}
+        return rec, out
+
+    def drain(self) -> None:
+        _check(lib().gconn_server_drain(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().gconn_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def to_u32(t: torch.Tensor) -> np.ndarray:

@@ -1,0 +1,151 @@
+"""GPU tests of the serving loop: every query batch's answers equal the
+oracle's for exactly the inserts submitted before it, whether the requests
+run one at a time or mixed and overlapping, under an in-flight budget far
+smaller than the offered work, with several client threads."""
+from __future__ import annotations
+
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _stream(n, seed, batches=40):
+    """Seeded request list: (kind, a, b); batch sizes log-uniform 1..20000."""
+    src, dst = graphgen.rmat_edges(15, 150_000, seed, n=n)
+    graphgen.shuffle_edges(src, dst, seed)
+    rng = np.random.default_rng(seed)
+    reqs, e = [], 0
+    while e < len(src) and len(reqs) < batches:
+        if rng.random() < 0.5:
+            k = int(10 ** rng.uniform(0, 4.3))
+            reqs.append((0, src[e:e + k].copy(), dst[e:e + k].copy()))
+            e += k
+        else:
+            a, b = graphgen.uniform_pairs(n, int(rng.integers(1, 3000)), seed, len(reqs))
+            # also ask about endpoints of edges inserted so far, and of later ones
+            j = rng.integers(0, len(src), size=200)
+            a = np.concatenate([a, src[j]])
+            b = np.concatenate([b, dst[j]])
+            reqs.append((1, a, b))
+    return reqs
+
+
+def _oracle_answers(n, reqs):
+    uf = oracle.UnionFind(n)
+    ans = []
+    for kind, a, b in reqs:
+        if kind == 0:
+            uf.insert(a, b)
+            ans.append(None)
+        else:
+            ans.append(uf.query(a, b))
+    return ans
+
+
+@pytest.mark.parametrize("link,find", [("async", "split"), ("rem_cas", "split"),
+                                       ("early", "halve"), ("ecl", "halve")])
+def test_server_mixed_equals_alone_equals_oracle(gpu_available, link, find):
+    from paper_2008_11839_amd import gconn as G
+    n = 20000
+    reqs = _stream(n, 11)
+    want = _oracle_answers(n, reqs)
+    opts = G.Options(sample="none", link=link, find=find)
+    # alone: one request at a time, each waited for before the next
+    srv = G.Server(n, streams=1, arena_bytes=1 << 20, options=opts)
+    alone = []
+    for kind, a, b in reqs:
+        rec, out = srv.wait(srv.submit(kind, a, b))
+        assert rec["status"] == 0
+        alone.append(out)
+    srv.close()
+    # mixed: all submitted at once, four streams, a budget of ~3 requests
+    srv = G.Server(n, streams=4, arena_bytes=600 << 10, options=opts)
+    tickets = [srv.submit(kind, a, b) for kind, a, b in reqs]
+    mixed, epochs, overlapped = [], [], 0
+    recs = []
+    for t in tickets:
+        rec, out = srv.wait(t, timeout=60.0)
+        assert rec["status"] == 0
+        mixed.append(out)
+        recs.append(rec)
+    srv.close()
+    for i, (kind, a, b) in enumerate(reqs):
+        if kind == 1:
+            assert np.array_equal(alone[i], want[i]), (link, i)
+            assert np.array_equal(mixed[i], want[i]), (link, i)
+    # epochs follow kind changes in submission order
+    kinds = [k for k, _, _ in reqs]
+    expect_epoch, e = [], 0
+    for i, k in enumerate(kinds):
+        if i == 0 or k != kinds[i - 1]:
+            e += 1
+        expect_epoch.append(e)
+    assert [r["epoch"] for r in recs] == expect_epoch
+    # admission happened while earlier requests were still running
+    for i in range(1, len(recs)):
+        if recs[i]["admit_us"] < recs[i - 1]["done_us"]:
+            overlapped += 1
+    say(f"[server] link={link} requests={len(reqs)} overlapped_admissions={overlapped}")
+    assert overlapped > 0
+
+
+def test_server_multithreaded_clients_total_order(gpu_available):
+    """Requests from several threads: the server orders them by submission;
+    replaying the recorded order through the oracle gives every answer."""
+    from paper_2008_11839_amd import gconn as G
+    n = 5000
+    srv = G.Server(n, streams=4, arena_bytes=256 << 10, options=G.Options(sample="none"))
+    lock = threading.Lock()
+    log = []  # (ticket, kind, a, b)
+
+    def client(seed):
+        reqs = _stream(n, seed, batches=25)
+        for kind, a, b in reqs:
+            with lock:  # record the submission order as the server sees it
+                t = srv.submit(kind, a, b)
+                log.append((t, kind, a, b))
+            time.sleep(0.0005 * (seed % 3))
+
+    threads = [threading.Thread(target=client, args=(s,)) for s in (21, 22, 23)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    got = {}
+    for t, kind, a, b in log:
+        rec, out = srv.wait(t, timeout=60.0)
+        assert rec["status"] == 0
+        got[t] = out
+    srv.close()
+    log.sort(key=lambda r: r[0])
+    want = _oracle_answers(n, [(k, a, b) for _, k, a, b in log])
+    for (t, kind, a, b), w in zip(log, want):
+        if kind == 1:
+            assert np.array_equal(got[t], w)
+
+
+def test_server_rejects_oversized_and_bad_requests(gpu_available):
+    from paper_2008_11839_amd import gconn as G
+    srv = G.Server(100, streams=2, arena_bytes=4096, options=G.Options(sample="none"))
+    with pytest.raises(G.GconnError):
+        srv.submit(0, np.zeros(1000, np.uint32), np.zeros(1000, np.uint32))  # 8000 B > arena
+    t = srv.submit(0, np.array([1, 2], np.uint32), np.array([2, 3], np.uint32))
+    rec, _ = srv.wait(t)
+    rec, out = srv.wait(srv.submit(1, np.array([1, 1], np.uint32), np.array([3, 4], np.uint32)))
+    assert out.tolist() == [1, 0]
+    srv.close()
+    with pytest.raises(G.GconnError):
+        G.Server(100, options=G.Options(sample="none", link="sv"))
