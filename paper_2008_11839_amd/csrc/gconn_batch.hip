@@ -234,7 +234,7 @@ BatchLayout plan_batch(const gconn_batch& b) {
   L.tiles = take(4 * (n / 64 + 1));
   L.lmax = take(4ull * b.num_graphs);
   const uint64_t groups = (n + 63) / 64;
-  L.sub_cap = (uint32_t)(((groups + kSubLists - 1) / kSubLists) * 64);
+  L.sub_cap = (uint32_t)(((groups + kSubLists - 1) / kSubLists + 1) * 64);
   L.small = take(4ull * kSubLists * L.sub_cap);
   L.medium = take(4ull * kSubLists * L.sub_cap);
   L.segs = take(8 * (2 * m / kSeg + 1));

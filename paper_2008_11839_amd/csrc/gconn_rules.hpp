@@ -33,6 +33,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// The rules are host-callable too, so that a CPU harness can run the very same
+// code from many threads (the atomic builtins below compile for both sides).
+#define GCONN_HD __host__ __device__ __forceinline__
+
 namespace gconn {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
@@ -48,22 +52,22 @@ enum UnionRule : int { kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnion
 #endif
 
 // Read of P inside a find / union loop (see the memory-model note above).
-__device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+GCONN_HD uint32_t ld(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, GCONN_P_LOAD_SCOPE);
 }
 // Device-coherent read (flags and counters polled across XCDs).
-__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+GCONN_HD uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
+GCONN_HD void st(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // CAS *p: expected -> desired.  On failure `expected` receives the current value.
-__device__ __forceinline__ bool cas(uint32_t* p, uint32_t& expected, uint32_t desired) {
+GCONN_HD bool cas(uint32_t* p, uint32_t& expected, uint32_t desired) {
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t amin(uint32_t* p, uint32_t v) {
+GCONN_HD uint32_t amin(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -76,7 +80,7 @@ struct LinkCtx {
   unsigned long long* hooks;  // successful-link counter (nullable)
 };
 
-__device__ __forceinline__ void record_link(const LinkCtx& c, uint32_t root, uint32_t u,
+GCONN_HD void record_link(const LinkCtx& c, uint32_t root, uint32_t u,
                                             uint32_t v) {
   // A root is linked at most once (it never becomes a root again), so the slot
   // write is uncontended.
@@ -84,12 +88,12 @@ __device__ __forceinline__ void record_link(const LinkCtx& c, uint32_t root, uin
     c.fu[root] = u;
     c.fv[root] = v;
   }
-  if (c.hooks) atomicAdd(c.hooks, 1ull);
+  if (c.hooks) __hip_atomic_fetch_add(c.hooks, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------ finds
 template <int F>
-__device__ __forceinline__ uint32_t find(uint32_t* P, uint32_t u) {
+GCONN_HD uint32_t find(uint32_t* P, uint32_t u) {
   if constexpr (F == kFindNaive) {
     uint32_t x = u;
     for (;;) {
@@ -98,14 +102,17 @@ __device__ __forceinline__ uint32_t find(uint32_t* P, uint32_t u) {
       x = p;
     }
   } else if constexpr (F == kFindSplit) {
+    // After the split step u moves to v, whose parent w was just read: it is
+    // carried into the next step instead of being read again.
+    uint32_t v = ld(&P[u]);
     for (;;) {
-      uint32_t v = ld(&P[u]);
       if (v == u) return u;
-      uint32_t w = ld(&P[v]);
+      const uint32_t w = ld(&P[v]);
       if (v == w) return v;
       uint32_t e = v;
       cas(&P[u], e, w);
       u = v;  // v < u
+      v = w;
     }
   } else if constexpr (F == kFindHalve) {
     for (;;) {
@@ -138,7 +145,7 @@ __device__ __forceinline__ uint32_t find(uint32_t* P, uint32_t u) {
 // smaller; on failure the CAS result is the new parent of the former root and
 // the search resumes from there.
 template <int F>
-__device__ __forceinline__ bool union_async(const LinkCtx& c, uint32_t u, uint32_t v) {
+GCONN_HD bool union_async(const LinkCtx& c, uint32_t u, uint32_t v) {
   uint32_t pu = find<F>(c.P, u), pv = find<F>(c.P, v);
   while (pu != pv) {
     if (pu < pv) {
@@ -162,7 +169,7 @@ __device__ __forceinline__ bool union_async(const LinkCtx& c, uint32_t u, uint32
 // hook target instead of waiting for the winner's write (a lane of the same
 // wave may be that winner, and lanes of one wave make no independent progress).
 template <int F>
-__device__ __forceinline__ bool union_hooks(const LinkCtx& c, uint32_t u, uint32_t v) {
+GCONN_HD bool union_hooks(const LinkCtx& c, uint32_t u, uint32_t v) {
   uint32_t pu = find<F>(c.P, u), pv = find<F>(c.P, v);
   while (pu != pv) {
     if (pu < pv) {
@@ -192,7 +199,7 @@ __device__ __forceinline__ bool union_hooks(const LinkCtx& c, uint32_t u, uint32
 // larger endpoint with a splitting step, and link it the moment it is a root.
 // Optional trailing finds compress both paths.
 template <int F>
-__device__ __forceinline__ bool union_early(const LinkCtx& c, uint32_t u, uint32_t v) {
+GCONN_HD bool union_early(const LinkCtx& c, uint32_t u, uint32_t v) {
   uint32_t pu = u, pv = v;
   bool linked = false;
   while (pu != pv) {
@@ -228,11 +235,16 @@ __device__ __forceinline__ bool union_early(const LinkCtx& c, uint32_t u, uint32
 // Union-Rem-CAS (Appendix A.2): compare the parents of the two current nodes;
 // the side with the larger parent either is a root (CAS it onto the other
 // side's parent) or takes one splice step towards its root.
+// The parents compared in each iteration are carried from the previous one:
+// after a split step the new r_u's parent is the value the step just read,
+// and r_v's side did not move.  A carried value can be older than a fresh
+// read, which the argument above already allows for; the hook itself is a CAS
+// that validates r_u is still a root.
 template <int F, int S>
-__device__ __forceinline__ bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
+GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
   uint32_t ru = u, rv = v;
+  uint32_t pru = ld(&c.P[ru]), prv = ld(&c.P[rv]);
   for (;;) {
-    uint32_t pru = ld(&c.P[ru]), prv = ld(&c.P[rv]);
     if (pru == prv) return false;
     if (pru < prv) {
       uint32_t t = ru;
@@ -254,12 +266,18 @@ __device__ __forceinline__ bool union_rem_cas(const LinkCtx& c, uint32_t u, uint
       }
       pru = e;  // ru was linked meanwhile: continue from its fresh parent
     }
-    uint32_t w = ld(&c.P[pru]);
+    const uint32_t w = ld(&c.P[pru]);
     if (w != pru) {
       uint32_t e = pru;
       cas(&c.P[ru], e, w);
     }
-    ru = (S == kSpliceSplitOne) ? pru : w;
+    if constexpr (S == kSpliceSplitOne) {
+      ru = pru;  // P[pru] = w was just read
+      pru = w;
+    } else {
+      ru = w;
+      pru = ld(&c.P[w]);
+    }
   }
 }
 
@@ -267,7 +285,7 @@ __device__ __forceinline__ bool union_rem_cas(const LinkCtx& c, uint32_t u, uint
 template <int U, int F, int S>
 struct Rule {
   static constexpr int kUnion = U, kFind = F, kSplice = S;
-  __device__ __forceinline__ static bool unite(const LinkCtx& c, uint32_t u, uint32_t v) {
+  GCONN_HD static bool unite(const LinkCtx& c, uint32_t u, uint32_t v) {
     if constexpr (U == kUnionAsync) return union_async<F>(c, u, v);
     else if constexpr (U == kUnionHooks) return union_hooks<F>(c, u, v);
     else if constexpr (U == kUnionEarly) return union_early<F>(c, u, v);

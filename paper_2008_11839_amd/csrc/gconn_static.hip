@@ -442,32 +442,53 @@ __global__ void __launch_bounds__(1024) k_lmax(const uint32_t* P, uint32_t n, ui
 // Full compression fused with vertex gathering.  mode 0: no sampling (P is the
 // identity, every vertex with edges is active); mode 1: P is already flat
 // (BFS sampling); mode 2: P[v] = root(v) first (k-out, hook-based).  Active:
-// degree > 0 and label != L_max (unless skip_lmax is 0).
+// degree > 0 and label != L_max (unless skip_lmax is 0).  Each lane takes four
+// consecutive vertices: their offsets and parents are all loaded before any
+// is used, and the four root chases advance together, so one wave keeps
+// several independent loads in flight instead of one dependent chain.
 template <typename OffT>
 __global__ void k_compress_gather(const OffT* __restrict__ off, uint32_t* P, uint32_t n, Ctrl* c,
                                   WorkLists wl, int mode, int skip_lmax, int want_stats) {
   const uint32_t lmax = skip_lmax ? c->lmax : kEmpty;
   unsigned long long act = 0, edges = 0;
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    const uint64_t v = base + lane();
-    uint64_t deg = 0;
-    bool active = false;
-    if (v < n) {
-      deg = (uint64_t)off[v + 1] - off[v];
-      uint32_t r = (uint32_t)v;
-      if (mode != 0) {
-        const uint32_t p = P[v];
-        r = p;
-        if (mode == 2 && p != v) {
-          r = root_plain(P, p);
-          if (r != p) P[v] = r;
-        }
+  for (uint64_t base = wave_base() * 4; base < n; base += wave_stride() * 4) {
+    const uint64_t v0 = base + 4 * lane();
+    uint64_t o[5];
+    uint32_t p[4], r[4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) o[k] = (v0 + k <= n) ? (uint64_t)off[v0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = (mode != 0 && v0 + k < n) ? P[v0 + k] : (uint32_t)(v0 + k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = p[k];
+    if (mode == 2) {
+      bool more = true;
+      while (more) {  // lockstep pointer jumping of the four chases
+        more = false;
+        uint32_t q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) q[k] = (r[k] != v0 + k && v0 + k < n) ? P[r[k]] : r[k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (q[k] != r[k]) {
+            r[k] = q[k];
+            more = true;
+          }
       }
-      active = deg > 0 && r != lmax;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (v0 + k < n && r[k] != p[k]) P[v0 + k] = r[k];
     }
-    wl_push(wl, c, base >> 6, (uint32_t)v, deg, active);
-    act += active ? 1 : 0;
-    edges += active ? deg : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool valid = v0 + k < n;
+      const uint64_t deg = valid ? o[k + 1] - o[k] : 0;
+      const bool active = valid && deg > 0 && r[k] != lmax;
+      // group (base / 64) + k: each push call covers at most 64 vertices
+      wl_push(wl, c, (base >> 6) + k, (uint32_t)(v0 + k), deg, active);
+      act += active ? 1 : 0;
+      edges += active ? deg : 0;
+    }
   }
   if (want_stats) {
     act = wave_sum(act);
@@ -1289,7 +1310,7 @@ struct Run {
   gconn_status gather() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
     const int mode = o.sample == GCONN_SAMPLE_NONE ? 0 : (o.sample == GCONN_SAMPLE_BFS ? 1 : 2);
-    k_compress_gather<OffT><<<gridN(g.n), block, 0, s>>>(off, P, g.n, ctrl, wl, mode,
+    k_compress_gather<OffT><<<gridN((g.n + 3) / 4), block, 0, s>>>(off, P, g.n, ctrl, wl, mode,
                                                          skip_lmax() ? 1 : 0, want_stats ? 1 : 0);
     GCONN_LAUNCHED("k_compress_gather");
     return GCONN_OK;
@@ -1566,8 +1587,10 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
   if (forest && !labels) L.P = take(4 * n);
   const bool csr = g.format == GCONN_CSR;
   if (csr) {
+    // push calls cover at most 64 items with group ids below ceil(n/256)*4
+    // <= ceil(n/64) + 3, so a sub-list gets at most ceil(ceil(n/64)/64) + 1 calls
     const uint64_t groups = (n + 63) / 64;
-    L.sub_cap = (uint32_t)(((groups + kSubLists - 1) / kSubLists) * 64);
+    L.sub_cap = (uint32_t)(((groups + kSubLists - 1) / kSubLists + 1) * 64);
     L.small = take(4ull * kSubLists * L.sub_cap);
     L.medium = take(4ull * kSubLists * L.sub_cap);
     // a vertex of degree d > kMedDeg (= kSeg) yields ceil(d / kSeg) <= 2d / kSeg segments

@@ -1,0 +1,86 @@
+// CPU stress harness for the union-find rules of the HIP library: the same
+// header (gconn_rules.hpp) compiled for the host, run from many std::threads
+// on one shared parent array.  Test infrastructure only.
+//
+//   rules_stress <edges.bin> <n> <rule> <threads> <labels.out>
+// edges.bin: uint32 pairs; rule: 0-3 Async (naive/split/halve/compress),
+// 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one).
+// Writes labels (root of every vertex, uint32) and prints the hook count.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
+#include <vector>
+
+#include "../../paper_2008_11839_amd/csrc/gconn_rules.hpp"
+
+using namespace gconn;
+
+template <class R>
+void run(const std::vector<uint32_t>& e, LinkCtx c, int threads) {
+  const size_t m = e.size() / 2;
+  std::vector<std::thread> ts;
+  for (int t = 0; t < threads; ++t)
+    ts.emplace_back([&, t] {
+      // interleaved slices so that threads race on the same regions
+      for (size_t i = t; i < m; i += threads) R::unite(c, e[2 * i], e[2 * i + 1]);
+    });
+  for (auto& th : ts) th.join();
+}
+
+int main(int argc, char** argv) {
+  if (argc != 6) return 2;
+  FILE* f = fopen(argv[1], "rb");
+  if (!f) return 3;
+  std::vector<uint32_t> e;
+  uint32_t buf[4096];
+  size_t got;
+  while ((got = fread(buf, 4, 4096, f)) > 0) e.insert(e.end(), buf, buf + got);
+  fclose(f);
+  const uint32_t n = (uint32_t)atoi(argv[2]);
+  const int rule = atoi(argv[3]), threads = atoi(argv[4]);
+  for (uint32_t x : e)
+    if (x >= n) return 4;
+  std::vector<uint32_t> P(n), H(n, kEmpty);
+  for (uint32_t v = 0; v < n; ++v) P[v] = v;
+  unsigned long long hooks = 0;
+  LinkCtx c{P.data(), H.data(), nullptr, nullptr, &hooks};
+  switch (rule) {
+    case 0: run<Rule<kUnionAsync, kFindNaive, 0>>(e, c, threads); break;
+    case 1: run<Rule<kUnionAsync, kFindSplit, 0>>(e, c, threads); break;
+    case 2: run<Rule<kUnionAsync, kFindHalve, 0>>(e, c, threads); break;
+    case 3: run<Rule<kUnionAsync, kFindCompress, 0>>(e, c, threads); break;
+    case 4: run<Rule<kUnionHooks, kFindNaive, 0>>(e, c, threads); break;
+    case 5: run<Rule<kUnionHooks, kFindSplit, 0>>(e, c, threads); break;
+    case 6: run<Rule<kUnionHooks, kFindHalve, 0>>(e, c, threads); break;
+    case 7: run<Rule<kUnionHooks, kFindCompress, 0>>(e, c, threads); break;
+    case 8: run<Rule<kUnionEarly, kFindNaive, 0>>(e, c, threads); break;
+    case 9: run<Rule<kUnionEarly, kFindSplit, 0>>(e, c, threads); break;
+    case 10: run<Rule<kUnionEarly, kFindHalve, 0>>(e, c, threads); break;
+    case 11: run<Rule<kUnionEarly, kFindCompress, 0>>(e, c, threads); break;
+    case 12: run<Rule<kUnionRemCas, kFindNaive, kSpliceSplitOne>>(e, c, threads); break;
+    case 13: run<Rule<kUnionRemCas, kFindSplit, kSpliceSplitOne>>(e, c, threads); break;
+    case 14: run<Rule<kUnionRemCas, kFindHalve, kSpliceSplitOne>>(e, c, threads); break;
+    case 15: run<Rule<kUnionRemCas, kFindNaive, kSpliceHalveOne>>(e, c, threads); break;
+    case 16: run<Rule<kUnionRemCas, kFindSplit, kSpliceHalveOne>>(e, c, threads); break;
+    case 17: run<Rule<kUnionRemCas, kFindHalve, kSpliceHalveOne>>(e, c, threads); break;
+    default: return 5;
+  }
+  std::vector<uint32_t> lab(n);
+  for (uint32_t v = 0; v < n; ++v) {
+    uint32_t r = v;
+    while (P[r] != r) {
+      if (P[r] > r) return 6;  // a parent must have a smaller id
+      r = P[r];
+    }
+    lab[v] = r;
+  }
+  FILE* o = fopen(argv[5], "wb");
+  if (!o) return 7;
+  fwrite(lab.data(), 4, n, o);
+  fclose(o);
+  printf("%llu\n", hooks);
+  return 0;
+}
