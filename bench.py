@@ -32,9 +32,9 @@ METRIC = "static CC Gedges/s on RMAT-24 (% HBM roofline); incremental updates/s 
 KERNEL_SOURCES = ["paper_2008_11839_amd/csrc/gconn_static.hip",
                   "paper_2008_11839_amd/csrc/gconn_rules.hpp"]
 # phase -> kernel launched in it (single-kernel phases)
-PHASE_KERNEL = {"init_ms": "k_init", "sample_ms": "k_sample_kout", "compress_ms": "k_compress",
-                "lmax_ms": "k_lmax", "gather_ms": "k_gather", "finish_ms": "k_finish_small+segs",
-                "finalize_ms": "k_compress(finalize)"}
+PHASE_KERNEL = {"init_ms": "k_init", "sample_ms": "k_sample_kout_pf", "lmax_ms": "k_lmax",
+                "gather_ms": "k_compress_gather", "finish_ms": "k_finish",
+                "finalize_ms": "k_finalize"}
 
 
 def log(*a):
@@ -54,14 +54,15 @@ def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
 
     init: write P (4n).  sample (k-out): read offsets (4(n+1)) and, per sampled
     entry, the neighbour id plus the two parent entries the union reads (12 B).
-    compress: read + write P (8n).  lmax: one label per sample.  gather: read
-    offsets and P (8n), write the active list (4A).  finish: offsets of the
-    active vertices (8A) and 12 B per finish entry.  finalize: read + write P.
+    lmax: one label per sample.  compress + gather (one kernel): read offsets
+    and P, write P (12n), write the active list (4A).  finish: offsets of the
+    active vertices (8A) and 12 B per finish entry.  finalize (active set only
+    after sampling): read the list, read + write P (12A).
     """
     Es, A, Ef = st["sampled_edges"], st["active_vertices"], st["finish_edges"]
-    return {"init_ms": 4 * n, "sample_ms": 4 * (n + 1) + 12 * Es, "compress_ms": 8 * n,
-            "lmax_ms": 4 * samples, "gather_ms": 8 * n + 4 * A, "finish_ms": 8 * A + 12 * Ef,
-            "finalize_ms": 8 * n}
+    return {"init_ms": 4 * n, "sample_ms": 4 * (n + 1) + 12 * Es, "lmax_ms": 4 * samples,
+            "gather_ms": 12 * n + 4 + 4 * A, "finish_ms": 8 * A + 12 * Ef,
+            "finalize_ms": 12 * A}
 
 
 def percentile(xs, p):
@@ -301,9 +302,9 @@ def main() -> int:
     ph = G.profile_read(reset=True)
     G.profile_enable(False)
     runs = max(ph.pop("runs"), 1)
-    phase_ms = {k: v / runs for k, v in ph.items()}
+    phase_ms = {k: v / runs for k, v in ph.items() if k in PHASE_KERNEL}
     abytes = algorithmic_bytes(n, m, st, opts.lmax_samples)
-    dominant = max((k for k in phase_ms if k != "finish_ms"), key=lambda k: phase_ms[k])
+    dominant = max(phase_ms, key=lambda k: phase_ms[k])
     dom_ms = phase_ms[dominant]
     achieved = abytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
     total_alg = sum(abytes.values())
