@@ -129,6 +129,11 @@ typedef struct gconn_options {
                             vertex's row prefetched (default), 1 one lane per
                             vertex, 2 lane-refill step machine (Union-Rem-CAS,
                             first-k, uint32 offsets; else as 0)            (0) */
+  int32_t atomic_compress; /* path-compression and splice writes (FindSplit,
+                            FindHalve, SplitAtomicOne, HalveAtomicOne, the
+                            Union-Early splice): 1 CAS as in the atomic rules,
+                            0 relaxed agent-scope stores (they only ever move
+                            a non-root's parent to one of its ancestors)  (1) */
 } gconn_options;
 
 /* Counters filled when a stats pointer is passed (the call then synchronises

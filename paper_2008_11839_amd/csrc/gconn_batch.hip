@@ -325,6 +325,7 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
   lc.H = nullptr;
   lc.fu = lc.fv = nullptr;
   lc.hooks = stats ? &ctrl->stat_hooks : nullptr;
+  lc.atomic_compress = 1;  // compression writes are CAS in the batch
   Ctrl* st = stats ? ctrl : nullptr;
   const uint32_t n = b->n, G = b->num_graphs, block = 256;
 

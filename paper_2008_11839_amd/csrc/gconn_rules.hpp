@@ -7,9 +7,9 @@
 // into a child, always of a smaller id, so no cycle can form.
 //
 // Memory model.  The eight XCDs of an MI355X each have a private L2 that is
-// not kept coherent with the others inside a kernel.  Every write to P is an
-// agent-scope atomic (CAS, min, store).  Reads of P inside find / union loops
-// are relaxed atomic loads whose scope is GCONN_P_LOAD_SCOPE; at workgroup
+// not kept coherent with the others inside a kernel.  Links (a root becoming a
+// child) are agent-scope CAS.  Reads of P inside find / union loops are relaxed
+// atomic loads whose scope is GCONN_P_LOAD_SCOPE; at wavefront or workgroup
 // scope they are ordinary cached loads (L2 hits for the hot entries near the
 // roots of large trees) and may return stale values.  Correctness never
 // depends on a read being fresh: any value P[x] has ever held is an ancestor
@@ -17,6 +17,18 @@
 // Progress does not depend on it either: every loop iteration below either
 // moves to a strictly smaller id, or continues from the value a failed CAS
 // returned (which is fresh), so no loop can spin on a stale line.
+//
+// Compression writes (the splitting / halving steps of the finds and the
+// splice steps) only ever touch a non-root x and set P[x] to an ancestor of x.
+// A non-root never becomes a root again and no link targets it, so such a
+// write needs no CAS: whatever order concurrent compression writes land in,
+// P[x] ends as some ancestor of x, which is all the forest needs.  With
+// LinkCtx::atomic_compress == 0 they are relaxed agent-scope stores, which
+// write through to memory like the atomics do; with 1 they are the CASes of
+// the atomic rules as written.  They must not be ordinary cached stores: an
+// XCD's L2 writes a dirty line back later, and on MI355X that write-back has
+// been measured to undo links that other XCDs made meanwhile on other words
+// of the same line (wrong labels at RMAT-24 scale).
 //
 // Readings of the appendix pseudocode (Appendix A.2, find / splice / union
 // algorithms) where it is garbled:
@@ -71,6 +83,15 @@ GCONN_HD uint32_t amin(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Compression write at non-root x: P[x] from `expected` to the ancestor
+// `desired`.  Returns whether P[x] now holds `desired`; a failed CAS leaves the
+// current value in `expected`.
+GCONN_HD bool shortcut(uint32_t* p, uint32_t& expected, uint32_t desired, bool atomic) {
+  if (atomic) return cas(p, expected, desired);
+  st(p, desired);
+  return true;
+}
+
 // Per-launch state shared by the rules.
 struct LinkCtx {
   uint32_t* P;         // parent array
@@ -78,6 +99,7 @@ struct LinkCtx {
   uint32_t* fu;        // spanning-forest slots (nullable)
   uint32_t* fv;
   unsigned long long* hooks;  // successful-link counter (nullable)
+  uint32_t atomic_compress;   // 1: compression writes are CAS; 0: relaxed stores
 };
 
 GCONN_HD void record_link(const LinkCtx& c, uint32_t root, uint32_t u,
@@ -93,7 +115,7 @@ GCONN_HD void record_link(const LinkCtx& c, uint32_t root, uint32_t u,
 
 // ------------------------------------------------------------------ finds
 template <int F>
-GCONN_HD uint32_t find(uint32_t* P, uint32_t u) {
+GCONN_HD uint32_t find(uint32_t* P, uint32_t u, bool ac) {
   if constexpr (F == kFindNaive) {
     uint32_t x = u;
     for (;;) {
@@ -110,7 +132,7 @@ GCONN_HD uint32_t find(uint32_t* P, uint32_t u) {
       const uint32_t w = ld(&P[v]);
       if (v == w) return v;
       uint32_t e = v;
-      cas(&P[u], e, w);
+      shortcut(&P[u], e, w, ac);
       u = v;  // v < u
       v = w;
     }
@@ -121,7 +143,7 @@ GCONN_HD uint32_t find(uint32_t* P, uint32_t u) {
       uint32_t w = ld(&P[v]);
       if (v == w) return v;
       uint32_t e = v;
-      u = cas(&P[u], e, w) ? w : e;  // the new P[u], smaller than u either way
+      u = shortcut(&P[u], e, w, ac) ? w : e;  // the new P[u], smaller than u either way
     }
   } else {  // kFindCompress
     uint32_t r = u;
@@ -146,7 +168,7 @@ GCONN_HD uint32_t find(uint32_t* P, uint32_t u) {
 // the search resumes from there.
 template <int F>
 GCONN_HD bool union_async(const LinkCtx& c, uint32_t u, uint32_t v) {
-  uint32_t pu = find<F>(c.P, u), pv = find<F>(c.P, v);
+  uint32_t pu = find<F>(c.P, u, c.atomic_compress), pv = find<F>(c.P, v, c.atomic_compress);
   while (pu != pv) {
     if (pu < pv) {
       uint32_t t = pu;
@@ -158,8 +180,8 @@ GCONN_HD bool union_async(const LinkCtx& c, uint32_t u, uint32_t v) {
       record_link(c, pu, u, v);
       return true;
     }
-    pu = find<F>(c.P, e);
-    pv = find<F>(c.P, pv);
+    pu = find<F>(c.P, e, c.atomic_compress);
+    pv = find<F>(c.P, pv, c.atomic_compress);
   }
   return false;
 }
@@ -170,7 +192,7 @@ GCONN_HD bool union_async(const LinkCtx& c, uint32_t u, uint32_t v) {
 // wave may be that winner, and lanes of one wave make no independent progress).
 template <int F>
 GCONN_HD bool union_hooks(const LinkCtx& c, uint32_t u, uint32_t v) {
-  uint32_t pu = find<F>(c.P, u), pv = find<F>(c.P, v);
+  uint32_t pu = find<F>(c.P, u, c.atomic_compress), pv = find<F>(c.P, v, c.atomic_compress);
   while (pu != pv) {
     if (pu < pv) {
       uint32_t t = pu;
@@ -189,8 +211,8 @@ GCONN_HD bool union_hooks(const LinkCtx& c, uint32_t u, uint32_t v) {
       }
       next = h;  // pu is being linked under h
     }
-    pu = find<F>(c.P, next);
-    pv = find<F>(c.P, pv);
+    pu = find<F>(c.P, next, c.atomic_compress);
+    pv = find<F>(c.P, pv, c.atomic_compress);
   }
   return false;
 }
@@ -221,13 +243,13 @@ GCONN_HD bool union_early(const LinkCtx& c, uint32_t u, uint32_t v) {
     uint32_t w = ld(&c.P[z]);
     if (w != z) {
       uint32_t e = z;
-      cas(&c.P[pu], e, w);
+      shortcut(&c.P[pu], e, w, c.atomic_compress);
     }
     pu = w;
   }
   if constexpr (F != kFindNaive) {
-    find<F>(c.P, u);
-    find<F>(c.P, v);
+    find<F>(c.P, u, c.atomic_compress);
+    find<F>(c.P, v, c.atomic_compress);
   }
   return linked;
 }
@@ -259,8 +281,8 @@ GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
       if (cas(&c.P[ru], e, prv)) {
         record_link(c, ru, u, v);
         if constexpr (F != kFindNaive) {
-          find<F>(c.P, u);
-          find<F>(c.P, v);
+          find<F>(c.P, u, c.atomic_compress);
+          find<F>(c.P, v, c.atomic_compress);
         }
         return true;
       }
@@ -269,7 +291,7 @@ GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
     const uint32_t w = ld(&c.P[pru]);
     if (w != pru) {
       uint32_t e = pru;
-      cas(&c.P[ru], e, w);
+      shortcut(&c.P[ru], e, w, c.atomic_compress);
     }
     if constexpr (S == kSpliceSplitOne) {
       ru = pru;  // P[pru] = w was just read

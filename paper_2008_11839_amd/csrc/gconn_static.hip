@@ -1055,10 +1055,10 @@ __global__ void k_bfs_label(const uint32_t* __restrict__ visited, uint32_t n, co
 // --------------------------------------------------------------- incremental
 template <class R>
 __global__ void k_query(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint64_t q,
-                        uint32_t* P, uint8_t* out) {
+                        uint32_t* P, uint8_t* out, int ac) {
   for (uint64_t i = gtid(); i < q; i += wave_stride()) {
-    const uint32_t ra = find<R::kFind>(P, a[i]);
-    const uint32_t rb = find<R::kFind>(P, b[i]);
+    const uint32_t ra = find<R::kFind>(P, a[i], ac != 0);
+    const uint32_t rb = find<R::kFind>(P, b[i], ac != 0);
     out[i] = (uint8_t)(ra == rb);
   }
 }
@@ -1166,6 +1166,7 @@ struct Run {
     c.fu = fu;
     c.fv = fv;
     c.hooks = want_stats ? &ctrl->stat_hooks : nullptr;
+    c.atomic_compress = (uint32_t)o.atomic_compress;
     return c;
   }
 
@@ -1455,6 +1456,7 @@ gconn_status launch_insert(const gconn_options& o, uint32_t* P, uint32_t* H, con
   c.H = H;
   c.fu = c.fv = nullptr;
   c.hooks = nullptr;
+  c.atomic_compress = (uint32_t)o.atomic_compress;
   const uint32_t block = (uint32_t)o.block;
   return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
     using R = decltype(rule);
@@ -1470,7 +1472,7 @@ gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a
   const uint32_t block = (uint32_t)o.block;
   return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
     using R = decltype(rule);
-    k_query<R><<<grid_for(q, block), block, 0, s>>>(a, b, q, P, out);
+    k_query<R><<<grid_for(q, block), block, 0, s>>>(a, b, q, P, out, o.atomic_compress);
     GCONN_LAUNCHED("k_query");
     return GCONN_OK;
   });

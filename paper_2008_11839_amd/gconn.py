@@ -48,7 +48,8 @@ class _Options(ctypes.Structure):
                 ("k", ctypes.c_uint32), ("hb_n", ctypes.c_uint32),
                 ("lmax_samples", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("kout_random", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("atomic_compress", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -186,6 +187,7 @@ class Options:
     validate: bool = False
     block: int = 256
     schedule: str = "auto"
+    atomic_compress: bool = True
 
     def to_c(self) -> _Options:
         o = _Options()
@@ -201,6 +203,7 @@ class Options:
         o.validate = int(self.validate)
         o.block = self.block
         o.schedule = SCHEDULE[self.schedule]
+        o.atomic_compress = int(self.atomic_compress)
         return o
 
 

@@ -2,7 +2,7 @@
 // header (gconn_rules.hpp) compiled for the host, run from many std::threads
 // on one shared parent array.  Test infrastructure only.
 //
-//   rules_stress <edges.bin> <n> <rule> <threads> <labels.out>
+//   rules_stress <edges.bin> <n> <rule> <threads> <labels.out> [atomic_compress]
 // edges.bin: uint32 pairs; rule: 0-3 Async (naive/split/halve/compress),
 // 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one).
 // Writes labels (root of every vertex, uint32) and prints the hook count.
@@ -31,7 +31,7 @@ void run(const std::vector<uint32_t>& e, LinkCtx c, int threads) {
 }
 
 int main(int argc, char** argv) {
-  if (argc != 6) return 2;
+  if (argc != 6 && argc != 7) return 2;
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 3;
   std::vector<uint32_t> e;
@@ -46,7 +46,8 @@ int main(int argc, char** argv) {
   std::vector<uint32_t> P(n), H(n, kEmpty);
   for (uint32_t v = 0; v < n; ++v) P[v] = v;
   unsigned long long hooks = 0;
-  LinkCtx c{P.data(), H.data(), nullptr, nullptr, &hooks};
+  const uint32_t ac = argc == 7 ? (uint32_t)atoi(argv[6]) : 1u;
+  LinkCtx c{P.data(), H.data(), nullptr, nullptr, &hooks, ac};
   switch (rule) {
     case 0: run<Rule<kUnionAsync, kFindNaive, 0>>(e, c, threads); break;
     case 1: run<Rule<kUnionAsync, kFindSplit, 0>>(e, c, threads); break;

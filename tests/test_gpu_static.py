@@ -89,8 +89,10 @@ def test_union_find_rules_all_samplers(cases):
         for sample in SAMPLERS:
             say(f"[uf] graph={name} n={C.n} m={C.m} sample={sample}")
             for link, find, splice in UF_RULES:
-                got = _labels(G, dg, sample=sample, link=link, find=find, splice=splice)
-                assert np.array_equal(got, want), (name, sample, link, find, splice)
+                for ac in (False, True):  # compression writes as stores / as CAS
+                    got = _labels(G, dg, sample=sample, link=link, find=find, splice=splice,
+                                  atomic_compress=ac)
+                    assert np.array_equal(got, want), (name, sample, link, find, splice, ac)
 
 
 def test_sv_and_label_propagation_all_samplers(cases):
@@ -217,8 +219,10 @@ def test_repeated_runs_under_contention(cases):
         say(f"[repeat] graph={name}")
         for rep in range(40):
             for link, find, splice in (("async", "split", "split_one"), ("rem_cas", "split", "split_one"),
-                                       ("hooks", "naive", "split_one"), ("early", "halve", "split_one")):
-                got = _labels(G, dg, sample="none", link=link, find=find, splice=splice)
+                                       ("hooks", "naive", "split_one"), ("early", "halve", "split_one"),
+                                       ("rem_cas", "halve", "halve_one")):
+                got = _labels(G, dg, sample="none", link=link, find=find, splice=splice,
+                              atomic_compress=rep % 2 == 1)
                 assert np.array_equal(got, want), (name, rep, link)
 
 
@@ -251,10 +255,11 @@ def test_incremental_batches_match_oracle_after_every_batch():
     src, dst = graphgen.rmat_edges(15, 60000, 21, n=n)
     graphgen.shuffle_edges(src, dst, 21)
     bounds = [0, 1, 10, 1000, 1001, 7000, 20000, 45000, len(src)]
-    for link, find, splice in UF_RULES:
-        say(f"[inc] link={link} find={find} splice={splice}")
+    for i_rule, (link, find, splice) in enumerate(UF_RULES):
+        ac = i_rule % 2 == 1  # alternate store / CAS compression writes
+        say(f"[inc] link={link} find={find} splice={splice} atomic_compress={ac}")
         inc = G.Incremental(n, options=G.Options(sample="none", link=link, find=find,
-                                                 splice=splice))
+                                                 splice=splice, atomic_compress=ac))
         uf = oracle.UnionFind(n)
         for i in range(len(bounds) - 1):
             lo, hi = bounds[i], bounds[i + 1]

@@ -1,6 +1,7 @@
 """The library's union-find rules (gconn_rules.hpp) compiled for the host and
 run concurrently from many threads: labels equal the oracle's, every parent
-points to a smaller id, and exactly n - c links succeed."""
+points to a smaller id, and exactly n - c links succeed, with compression
+writes as CAS and as relaxed stores."""
 from __future__ import annotations
 
 import os
@@ -24,9 +25,11 @@ def harness():
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
+    tmp = f"{BIN}.{os.getpid()}"  # parallel workers each build, then rename
     subprocess.run([hipcc, "-O2", "-std=c++17", "-pthread", "--offload-arch=gfx950",
                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                    SRC, "-o", BIN], check=True, capture_output=True)
+                    SRC, "-o", tmp], check=True, capture_output=True)
+    os.replace(tmp, BIN)
     return BIN
 
 
@@ -42,8 +45,9 @@ def _graphs():
     yield "grid", g.n, np.stack([src, dst], 1)
 
 
+@pytest.mark.parametrize("atomic_compress", [1, 0])
 @pytest.mark.parametrize("rule", RULES)
-def test_rules_concurrent_on_cpu(harness, tmp_path, rule):
+def test_rules_concurrent_on_cpu(harness, tmp_path, rule, atomic_compress):
     for name, n, edges in _graphs():
         ef = tmp_path / f"{name}.bin"
         edges.astype(np.uint32).tofile(ef)
@@ -51,7 +55,8 @@ def test_rules_concurrent_on_cpu(harness, tmp_path, rule):
         c = int((want == np.arange(n, dtype=np.uint32)).sum())
         for threads in (2, 8, 32):
             out = tmp_path / "labels.bin"
-            r = subprocess.run([harness, str(ef), str(n), str(rule), str(threads), str(out)],
+            r = subprocess.run([harness, str(ef), str(n), str(rule), str(threads), str(out),
+                                str(atomic_compress)],
                                capture_output=True, text=True, timeout=120)
             assert r.returncode == 0, (name, rule, threads, r.returncode)
             got = np.fromfile(out, np.uint32)
