@@ -134,6 +134,13 @@ typedef struct gconn_options {
                             Union-Early splice): 1 CAS as in the atomic rules,
                             0 relaxed agent-scope stores (they only ever move
                             a non-root's parent to one of its ancestors)  (1) */
+  int32_t kout_prelink;  /* first-k k-out with k <= 2: 1 links every vertex to
+                            its smallest sampled neighbour, when that is smaller,
+                            with one plain store before any union runs (each
+                            vertex is still a root and the only writer of its
+                            own slot), and sends only its other sampled edge(s)
+                            through the union rule; 0 unites every sampled edge.
+                            Same partition either way.                     (0) */
 } gconn_options;
 
 /* Counters filled when a stats pointer is passed (the call then synchronises

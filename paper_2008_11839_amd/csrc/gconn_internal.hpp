@@ -65,6 +65,7 @@ struct WsLayout {
   size_t visited = 0; // BFS bitmap
   size_t fr_bits0 = 0, fr_bits1 = 0;  // BFS frontier bitmaps
   size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
+  size_t resid = 0;   // k-out pre-link: residual sampled edges (uint2[n])
   uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;

@@ -196,6 +196,66 @@ __global__ void k_sample_kout_pf(const OffT* __restrict__ off, const uint32_t* _
   }
 }
 
+// k-out pre-link (first k <= 2 edges).  Runs before any union: every vertex v
+// is still a root and this lane is the only writer of P[v], so linking v under
+// its smallest sampled neighbour u < v is a plain store (it is a link of the
+// root v by the edge (v, u), recorded in v's forest slot).  The other sampled
+// edges of v (self-loops and repeats dropped) go to res[v] for the union pass.
+// The partition after both passes is that of the sampled edge set, as with
+// one union per sampled edge.
+template <typename OffT>
+__global__ void k_kout_prelink(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                               uint32_t n, uint32_t k, uint32_t* P, uint2* res, uint32_t* fu,
+                               uint32_t* fv, Ctrl* stats) {
+  unsigned long long sampled = 0, linked = 0;
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    const uint64_t v = base + lane();
+    if (v < n) {
+      const uint64_t b = off[v], d = (uint64_t)off[v + 1] - b;
+      uint32_t a = kEmpty, c = kEmpty;
+      if (d > 0) a = nbrs[b];
+      if (d > 1 && k > 1) c = nbrs[b + 1];
+      sampled += d < k ? d : k;
+      if (a == v) a = kEmpty;
+      if (c == v || c == a) c = kEmpty;
+      const uint32_t lo = a < c ? a : c, hi = a < c ? c : a;  // kEmpty sorts last
+      uint2 r = make_uint2(kEmpty, kEmpty);
+      if (lo < v) {
+        P[v] = lo;
+        if (fu) {
+          fu[v] = (uint32_t)v;
+          fv[v] = lo;
+        }
+        ++linked;
+        r.x = hi;
+      } else {
+        r.x = lo;
+        r.y = hi;
+      }
+      res[v] = r;
+    }
+  }
+  if (stats) {
+    // every lane of the wave ran the same iterations
+    sampled = wave_sum(sampled);
+    linked = wave_sum(linked);
+    if (lane() == 0) {
+      if (sampled) atomicAdd(&stats->stat_sampled, sampled);
+      if (linked) atomicAdd(&stats->stat_hooks, linked);
+    }
+  }
+}
+
+// Union pass over the residual sampled edges of the pre-link.
+template <class R>
+__global__ void k_kout_residual(const uint2* __restrict__ res, uint32_t n, LinkCtx lc) {
+  for (uint64_t v = gtid(); v < n; v += wave_stride()) {
+    const uint2 r = res[v];
+    if (r.x != kEmpty) R::unite(lc, (uint32_t)v, r.x);
+    if (r.y != kEmpty) R::unite(lc, (uint32_t)v, r.y);
+  }
+}
+
 // The same first-k sampling with Union-Rem-CAS as a lane-refill step machine
 // (uint32 offsets).  Each iteration: pick at most two addresses from the
 // lane's state, load them together, decide, issue at most one CAS, update the
@@ -350,7 +410,7 @@ __global__ void k_hb_step1(const OffT* __restrict__ off, const uint32_t* __restr
                            uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv, Ctrl* stats) {
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
     uint64_t v = base + lane();
-    uint32_t took = 0;
+    uint32_t took = 0, linked = 0;
     if (v < n) {
       uint64_t b = off[v];
       if ((uint64_t)off[v + 1] > b) {
@@ -358,6 +418,7 @@ __global__ void k_hb_step1(const OffT* __restrict__ off, const uint32_t* __restr
         uint32_t w = nbrs[b];
         if (w < v) {
           P[v] = w;
+          linked = 1;
           if (fu) {
             fu[v] = (uint32_t)v;
             fv[v] = w;
@@ -366,8 +427,9 @@ __global__ void k_hb_step1(const OffT* __restrict__ off, const uint32_t* __restr
       }
     }
     if (stats) {
-      unsigned long long s = wave_sum(took);
+      unsigned long long s = wave_sum(took), l = wave_sum(linked);
       if (lane() == 0 && s) atomicAdd(&stats->stat_sampled, s);
+      if (lane() == 0 && l) atomicAdd(&stats->stat_hooks, l);
     }
   }
 }
@@ -1068,6 +1130,11 @@ namespace {
 
 constexpr uint32_t kPersistentBlocks = 2048;  // round kernels: 256 CUs x 8 workgroups
 
+// The k-out pre-link covers first-k sampling with k <= 2.
+bool kout_prelink_applies(const gconn_options& o) {
+  return o.kout_prelink && o.sample == GCONN_SAMPLE_KOUT && !o.kout_random && o.k <= 2;
+}
+
 template <class Fn>
 gconn_status with_rule(int link, int find_rule, int splice, Fn&& fn) {
   switch (link) {
@@ -1188,7 +1255,18 @@ struct Run {
     Ctrl* st = want_stats ? ctrl : nullptr;
     GCONN_TRY(prof_mark(kPhaseSample, true, s));
     if (o.sample == GCONN_SAMPLE_KOUT) {
-      if (kout_step_machine()) {
+      if (kout_prelink_applies(o)) {
+        uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
+        const uint32_t pgrid = std::min<uint32_t>(gridN(n), 8192);
+        k_kout_prelink<OffT><<<pgrid, block, 0, s>>>(off, g.nbrs, n, o.k, P, res, fu, fv, st);
+        GCONN_LAUNCHED("k_kout_prelink");
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          k_kout_residual<R><<<gridN(n), block, 0, s>>>(res, n, link_ctx());
+          GCONN_LAUNCHED("k_kout_residual");
+          return GCONN_OK;
+        }));
+      } else if (kout_step_machine()) {
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
           using R = decltype(rule);
           auto kern = k_sample_kout_rem_sm<R::kFind, R::kSplice>;
@@ -1600,6 +1678,7 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
     L.segs = take(8 * L.seg_cap);
   }
   if (o.link == GCONN_LINK_HOOKS) L.hooks = take(4 * n);
+  if (csr && kout_prelink_applies(o)) L.resid = take(8 * n);
   const bool iterative =
       o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
   if (iterative) {

@@ -49,7 +49,7 @@ class _Options(ctypes.Structure):
                 ("lmax_samples", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("kout_random", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("atomic_compress", ctypes.c_int32)]
+                ("atomic_compress", ctypes.c_int32), ("kout_prelink", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -188,6 +188,7 @@ class Options:
     block: int = 256
     schedule: str = "auto"
     atomic_compress: bool = True
+    kout_prelink: bool = False
 
     def to_c(self) -> _Options:
         o = _Options()
@@ -204,6 +205,7 @@ class Options:
         o.block = self.block
         o.schedule = SCHEDULE[self.schedule]
         o.atomic_compress = int(self.atomic_compress)
+        o.kout_prelink = int(self.kout_prelink)
         return o
 
 

@@ -41,17 +41,20 @@ def rmat22(gpu_available):
     return C, G.csr(C.offsets, C.nbrs, C.n), want
 
 
+@pytest.mark.parametrize("prelink", [False, True])
 @pytest.mark.parametrize("ac", [True, False])
-def test_rmat22_labels_match_oracle(rmat22, ac):
+def test_rmat22_labels_match_oracle(rmat22, ac, prelink):
     import torch
     from paper_2008_11839_amd import gconn as G
     C, dg, want = rmat22
     c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
     for cfg in CONFIGS:
-        o = G.Options(atomic_compress=ac, **cfg)
+        if prelink and cfg["sample"] != "kout":
+            continue
+        o = G.Options(atomic_compress=ac, kout_prelink=prelink, **cfg)
         ws = G.alloc_workspace(G.workspace_size(dg, o))
         for rep in range(3):
-            say(f"[rmat22] {cfg} atomic_compress={ac} rep={rep}")
+            say(f"[rmat22] {cfg} atomic_compress={ac} prelink={prelink} rep={rep}")
             lab, st = G.cc(dg, options=o, workspace=ws, stats=True)
             torch.cuda.synchronize()
             got = G.to_u32(lab)
@@ -61,12 +64,14 @@ def test_rmat22_labels_match_oracle(rmat22, ac):
                 assert st["hooks"] == C.n - c, (cfg, ac, rep)
 
 
+@pytest.mark.parametrize("prelink", [False, True])
 @pytest.mark.parametrize("ac", [True, False])
-def test_rmat22_spanning_forest(rmat22, ac):
+def test_rmat22_spanning_forest(rmat22, ac, prelink):
     import torch
     from paper_2008_11839_amd import gconn as G
     C, dg, want = rmat22
-    o = G.Options(sample="kout", link="rem_cas", find="split", atomic_compress=ac)
+    o = G.Options(sample="kout", link="rem_cas", find="split", atomic_compress=ac,
+                  kout_prelink=prelink)
     fu, fv, lab = G.spanning_forest(dg, options=o)
     torch.cuda.synchronize()
     fu, fv = G.to_u32(fu), G.to_u32(fv)

@@ -360,3 +360,39 @@ def test_random_kout_and_larger_k(cases):
                         got = _labels(G, dg, sample="kout", k=k, kout_random=random, link=link,
                                       schedule=sched, seed=7)
                         assert np.array_equal(got, want), (name, k, random, link, sched)
+
+
+def test_kout_prelink(cases):
+    """k-out with the contention-free pre-link pass: labels, sampled-edge count,
+    L_max, active set and hook count equal the oracle's; the spanning forest is
+    valid and fills exactly the non-minimum slots; k = 3 and random picks fall
+    back to one union per sampled edge."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    for name, (C, dg, want) in cases.items():
+        c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
+        roots_mask = want != np.arange(C.n, dtype=np.uint32)
+        for k in (1, 2):
+            s_lab, e = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
+            L = oracle.lmax(s_lab, 1024, 1)
+            for link, find, splice in UF_RULES + [("sv", "split", "split_one")]:
+                for ac in (False, True):
+                    say(f"[prelink] graph={name} k={k} link={link} find={find} splice={splice} ac={ac}")
+                    o = G.Options(sample="kout", link=link, find=find, splice=splice, k=k,
+                                  atomic_compress=ac, kout_prelink=True)
+                    lab, st = G.cc(dg, options=o, stats=True)
+                    assert np.array_equal(G.to_u32(lab), want), (name, k, link, find, splice, ac)
+                    if C.m:
+                        assert st["sampled_edges"] == e
+                        assert st["lmax"] == L
+                        assert st["active_vertices"] == oracle.active_count(C.n, C.offsets, s_lab, L)
+                    if link not in ("sv", "ecl"):
+                        assert st["hooks"] == C.n - c, (name, k, link)
+                        fu, fv, _ = G.spanning_forest(dg, want_labels=False, options=o)
+                        torch.cuda.synchronize()
+                        fu, fv = G.to_u32(fu), G.to_u32(fv)
+                        oracle.check_forest(C.n, C.offsets, C.nbrs, fu, fv, want)
+                        assert np.array_equal(fu != G.EMPTY, roots_mask), (name, k, link)
+        for k, random in ((3, False), (2, True)):
+            got = _labels(G, dg, sample="kout", k=k, kout_random=random, kout_prelink=True)
+            assert np.array_equal(got, want), (name, k, random)
