@@ -227,6 +227,10 @@ def main() -> int:
                     help="largest graph of the many-graph batch (the full workload uses 1e6)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="cap on served requests (0: the whole edge stream)")
+    ap.add_argument("--traffic-workload", action="store_true",
+                    help="only run the workload the HBM-counter passes profile: three static CC "
+                         "runs of the benchmark configuration, then three 1 GiB copies that "
+                         "calibrate the counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -261,6 +265,18 @@ def main() -> int:
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ws = G.alloc_workspace(G.workspace_size(dg, opts))
     stream = torch.cuda.current_stream()
+
+    if args.traffic_workload:
+        for _ in range(3):
+            G.cc(dg, labels=labels, options=opts, workspace=ws)
+        torch.cuda.synchronize()
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1, out=b)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        log("traffic workload done")
+        return 0
 
     # ------------------------------------------------------------ stats + parity (untimed)
     lab, st = G.cc(dg, labels=labels, options=opts, workspace=ws, stats=True)
@@ -311,7 +327,7 @@ def main() -> int:
     log(f"phases (ms): {json.dumps({k: round(v, 4) for k, v in phase_ms.items()})}")
 
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_rmat24.json")
+    tpath = os.path.join(ROOT, "profiles", "traffic_rmat24.txt")
     if os.path.exists(tpath):
         with open(tpath) as f:
             rec = json.load(f)
