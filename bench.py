@@ -216,6 +216,8 @@ def main() -> int:
     ap.add_argument("--find", default="split")
     ap.add_argument("--splice", default="split_one")
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--kout-prelink", type=int, default=0, choices=(0, 1))
+    ap.add_argument("--atomic-compress", type=int, default=1, choices=(0, 1))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the spanning-forest and incremental measurements")
@@ -261,7 +263,8 @@ def main() -> int:
     dg = G.csr(C.offsets, C.nbrs, n)  # uint32 offsets (m < 2^32)
     torch.cuda.synchronize()
     opts = G.Options(sample=args.sample, link=args.link, find=args.find, splice=args.splice,
-                     block=args.block)
+                     block=args.block, kout_prelink=bool(args.kout_prelink),
+                     atomic_compress=bool(args.atomic_compress))
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ws = G.alloc_workspace(G.workspace_size(dg, opts))
     stream = torch.cuda.current_stream()
@@ -320,6 +323,8 @@ def main() -> int:
     runs = max(ph.pop("runs"), 1)
     phase_ms = {k: v / runs for k, v in ph.items() if k in PHASE_KERNEL}
     abytes = algorithmic_bytes(n, m, st, opts.lmax_samples)
+    if args.kout_prelink and args.sample == "kout":
+        PHASE_KERNEL["sample_ms"] = "k_kout_prelink+k_kout_residual"
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     dom_ms = phase_ms[dominant]
     achieved = abytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
@@ -353,6 +358,7 @@ def main() -> int:
                                f"scrambled ids, symmetrised CSR, seed {args.seed}",
                    "n": n, "m_directed": m, "sample": args.sample, "link": args.link,
                    "find": args.find, "splice": args.splice, "block": args.block,
+                   "kout_prelink": args.kout_prelink, "atomic_compress": args.atomic_compress,
                    "parity_vs_oracle": parity},
         "roofline": roofline,
         "phases_ms": {k: round(v, 5) for k, v in phase_ms.items()},

@@ -114,8 +114,10 @@ GCONN_HD void record_link(const LinkCtx& c, uint32_t root, uint32_t u,
 }
 
 // ------------------------------------------------------------------ finds
+// pu: a value P[u] is known to have held (kEmpty: read it).  Any such value is
+// an ancestor of u, so the walk may start from it.
 template <int F>
-GCONN_HD uint32_t find(uint32_t* P, uint32_t u, bool ac) {
+GCONN_HD uint32_t find(uint32_t* P, uint32_t u, bool ac, uint32_t pu = kEmpty) {
   if constexpr (F == kFindNaive) {
     uint32_t x = u;
     for (;;) {
@@ -126,7 +128,7 @@ GCONN_HD uint32_t find(uint32_t* P, uint32_t u, bool ac) {
   } else if constexpr (F == kFindSplit) {
     // After the split step u moves to v, whose parent w was just read: it is
     // carried into the next step instead of being read again.
-    uint32_t v = ld(&P[u]);
+    uint32_t v = pu != kEmpty ? pu : ld(&P[u]);
     for (;;) {
       if (v == u) return u;
       const uint32_t w = ld(&P[v]);
@@ -138,7 +140,8 @@ GCONN_HD uint32_t find(uint32_t* P, uint32_t u, bool ac) {
     }
   } else if constexpr (F == kFindHalve) {
     for (;;) {
-      uint32_t v = ld(&P[u]);
+      uint32_t v = pu != kEmpty ? pu : ld(&P[u]);
+      pu = kEmpty;
       if (v == u) return u;
       uint32_t w = ld(&P[v]);
       if (v == w) return v;
@@ -281,8 +284,10 @@ GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
       if (cas(&c.P[ru], e, prv)) {
         record_link(c, ru, u, v);
         if constexpr (F != kFindNaive) {
-          find<F>(c.P, u, c.atomic_compress);
-          find<F>(c.P, v, c.atomic_compress);
+          // P[ru] is now prv, and prv was read as P[rv]: an endpoint that is
+          // ru or rv starts its compressing find from prv.
+          find<F>(c.P, u, c.atomic_compress, (u == ru || u == rv) ? prv : kEmpty);
+          find<F>(c.P, v, c.atomic_compress, (v == ru || v == rv) ? prv : kEmpty);
         }
         return true;
       }
