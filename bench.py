@@ -344,6 +344,10 @@ def main() -> int:
         "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": traffic,
+        # measured line traffic of the same kernel over its time: how busy HBM really is
+        "traffic_gbs": round(traffic / (dom_ms * 1e-3) / 1e9, 1) if traffic and dom_ms > 0 else None,
+        "traffic_frac": round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        if traffic and dom_ms > 0 else None,
         "alg_bytes_per_launch": abytes[dominant], "launch_ms": round(dom_ms, 5),
         "step_alg_bytes": total_alg,
         "step_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
