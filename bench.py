@@ -203,6 +203,55 @@ def batched_bench(G, args) -> dict:
             "labels_identical": bool(same)}
 
 
+def mixed_bench(G, args) -> dict:
+    """Mixed insert/query batches over a Barabasi-Albert edge stream, for several
+    insert-to-query ratios (the paper's mixed-batch experiment): device-resident
+    batches of 2^20 elements, inserts of a batch applied before its queries."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import oracle
+    dev = torch.device("cuda", 0)
+    n, k = 1 << args.mixed_scale, 10
+    src, dst = graphgen.ba_edges(n, k, args.seed)
+    want = oracle.cc_coo(n, src, dst)
+    B = 1 << 20
+    out = {"workload": f"Barabasi-Albert n=2^{args.mixed_scale}, {k} edges per arriving vertex "
+                       f"({len(src)} inserts, shuffled), uniform query pairs, batches of {B} "
+                       "elements, Union-Async + FindSplit, device-resident", "ratios": {}}
+    for ratio in (4.0, 1.0, 0.25):
+        kind, a, b = graphgen.mixed_stream(src, dst, n, ratio, args.seed)
+        kt = torch.from_numpy(kind).to(dev)
+        at = torch.from_numpy(a.view(np.int32)).to(dev)
+        bt = torch.from_numpy(b.view(np.int32)).to(dev)
+        res = torch.empty(len(kind), dtype=torch.uint8, device=dev)
+        inc = G.Incremental(n, options=G.Options(sample="none", link="async", find="split"))
+        torch.cuda.synchronize()
+        evs = []
+        w0 = time.perf_counter()
+        for lo in range(0, len(kind), B):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            inc.mixed(kt[lo:lo + B], at[lo:lo + B], bt[lo:lo + B], out=res[lo:lo + B])
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        lat = [x.elapsed_time(y) for x, y in evs]
+        ok = bool(np.array_equal(G.to_u32(inc.labels()), want))
+        inc.close()
+        out["ratios"][str(ratio)] = {
+            "elements": len(kind), "queries": int(kind.sum()),
+            "elements_per_s": round(len(kind) / (sum(lat) * 1e-3), 1),
+            "wall_elements_per_s": round(len(kind) / wall, 1),
+            "batch_ms_p50": round(percentile(lat, 50), 4),
+            "batch_ms_p99": round(percentile(lat, 99), 4),
+            "labels_match_oracle": ok}
+        del kt, at, bt, res
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +273,9 @@ def main() -> int:
     ap.add_argument("--inc-batch", type=int, default=1_000_000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-scale", type=int, default=22,
+                    help="Barabasi-Albert stream of 2^scale vertices, 10 edges each")
     ap.add_argument("--batch-graphs", type=int, default=2000)
     ap.add_argument("--batch-nmax", type=float, default=1e5,
                     help="largest graph of the many-graph batch (the full workload uses 1e6)")
@@ -448,6 +500,11 @@ def main() -> int:
         }
         log(f"incremental {result['incremental']}")
         del s_in, d_in
+
+    # ------------------------------------------------------------ mixed insert/query batches
+    if not args.no_extras and not args.no_mixed:
+        result["incremental_mixed"] = mixed_bench(G, args)
+        log(f"incremental_mixed {result['incremental_mixed']}")
 
     # ------------------------------------------------------------ serving loop (host-fed)
     if not args.no_extras and not args.no_serving:

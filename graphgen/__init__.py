@@ -71,6 +71,8 @@ def _load():
                                           ctypes.c_int, u64p, u32p]
         lib.gg_shuffle_edges.restype = None
         lib.gg_shuffle_edges.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u32p, u32p]
+        lib.gg_ba_edges.restype = ctypes.c_int64
+        lib.gg_ba_edges.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, u32p, u32p]
         lib.gg_uniform_pairs.restype = None
         lib.gg_uniform_pairs.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_uint64, u32p, u32p]
@@ -178,6 +180,32 @@ def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray, symmetrize: bool = 
 
 def shuffle_edges(src: np.ndarray, dst: np.ndarray, seed: int) -> None:
     _load().gg_shuffle_edges(len(src), seed, _p32(src), _p32(dst))
+
+
+def ba_edges(n: int, k: int, seed: int):
+    """Barabasi-Albert edges in arrival order: vertex v attaches k edges to
+    earlier endpoints in proportion to degree (self-loops dropped)."""
+    src = np.empty(max(n * k, 1), np.uint32)
+    dst = np.empty(max(n * k, 1), np.uint32)
+    w = _load().gg_ba_edges(n, k, seed, _p32(src), _p32(dst))
+    return src[:w].copy(), dst[:w].copy()
+
+
+def mixed_stream(src: np.ndarray, dst: np.ndarray, n: int, ratio: float, seed: int):
+    """Insert edges shuffled together with uniform query pairs, 1/ratio queries
+    per insert (ratio = inserts per query).  Returns (kind, a, b) with kind 0 for
+    an insert and 1 for a query, in stream order."""
+    k = len(src)
+    q = int(round(k / ratio)) if ratio > 0 else 0
+    qa, qb = uniform_pairs(n, q, seed, 77)
+    kind = np.concatenate([np.zeros(k, np.uint32), np.ones(q, np.uint32)])
+    a = np.concatenate([src, qa])
+    b = np.concatenate([dst, qb])
+    # one permutation applied to all three arrays: shuffle (kind, index) pairs
+    idx = np.arange(k + q, dtype=np.uint32)
+    tag = kind.copy()
+    shuffle_edges(idx, tag, seed)
+    return kind[idx].astype(np.uint8), a[idx], b[idx]
 
 
 def uniform_pairs(n: int, q: int, seed: int, stream: int = 0):

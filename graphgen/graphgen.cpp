@@ -16,6 +16,10 @@
 //     per level, optional seeded bijective id scramble (Graph500 style),
 //     rejection of ids >= n when n is not a power of two.
 //   * 2D / 3D bond-percolation grids: each lattice edge kept i.i.d. with prob p.
+//   * Barabasi-Albert preferential attachment, drawn with the Batagelj-Brandes
+//     edge-copy method (Phys. Rev. E 71, 036113, 2005): edge slot j of vertex v
+//     attaches v to the endpoint in a uniform earlier slot of the endpoint list,
+//     which picks targets in proportion to degree.
 // Build: g++ -O2 -fopenmp -shared -fPIC (no -march=native: the library travels).
 #include <algorithm>
 #include <cmath>
@@ -264,6 +268,33 @@ void gg_shuffle_edges(uint64_t k, uint64_t seed, uint32_t* src, uint32_t* dst) {
     std::swap(src[i - 1], src[j]);
     std::swap(dst[i - 1], dst[j]);
   }
+}
+
+// Barabasi-Albert stream: vertex v = 0..n-1 arrives with k edges, in order.
+// The endpoint list holds 2 entries per edge slot (v, target); slot e of the
+// list draws r uniform in [0, 2e] and copies the endpoint stored at r (the
+// first slot copies itself, a self-loop).  Self-loops are dropped, duplicates
+// kept; edges come out in arrival order (sequential by construction).
+int64_t gg_ba_edges(uint32_t n, uint32_t k, uint64_t seed, uint32_t* src, uint32_t* dst) {
+  if (n == 0 || k == 0) return 0;
+  const uint64_t key = gg_key(seed, 6);
+  const uint64_t slots = (uint64_t)n * k;
+  std::vector<uint32_t> target(slots);
+  for (uint64_t e = 0; e < slots; ++e) {
+    const uint64_t r = (uint64_t)(((unsigned __int128)draw(key, e) * (2 * e + 1)) >> 64);
+    // even entry 2s: the vertex arriving with slot s; odd entry 2s+1: its target
+    target[e] = (r & 1) ? target[r / 2] : (uint32_t)((r / 2) / k);
+  }
+  uint64_t w = 0;
+  for (uint64_t e = 0; e < slots; ++e) {
+    const uint32_t v = (uint32_t)(e / k);
+    if (target[e] != v) {
+      src[w] = v;
+      dst[w] = target[e];
+      ++w;
+    }
+  }
+  return (int64_t)w;
 }
 
 // Uniform vertex pairs (query batches).

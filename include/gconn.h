@@ -85,7 +85,12 @@ enum {
 };
 
 /* Splice rule of Union-Rem-CAS at a non-root (Appendix A.2, splice options). */
-enum { GCONN_SPLICE_SPLIT_ONE = 0, GCONN_SPLICE_HALVE_ONE = 1 };
+/* SPLICE_ATOMIC: Rem's splice, done with a CAS (Appendix A.2, Union-Rem-CAS
+ * splice options): a non-root r_u whose parent is above P[r_v] is re-hung
+ * under P[r_v] and the walk continues from its old parent.  Correct when
+ * unions and queries are separated, which every call of this library is
+ * (static runs; epoch-fenced incremental batches). */
+enum { GCONN_SPLICE_SPLIT_ONE = 0, GCONN_SPLICE_HALVE_ONE = 1, GCONN_SPLICE_ATOMIC = 2 };
 
 /* Liu-Tarjan variants, in the paper's order (Appendix A.4): connect rule
  * C(onnect)/P(arentConnect)/E(xtendedConnect), update rule U(pdate)/R(ootUpdate),
@@ -179,7 +184,8 @@ gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspac
  * edge that linked it; other slots hold 0xFFFFFFFF.  Exactly n - c slots are
  * filled (c = number of components).  labels_out (device, nullable) receives
  * the canonical labels as in gconn_cc.  Root-based finishes only: union-find
- * rules and SV (LT and LP return GCONN_EUNSUPPORTED). */
+ * rules and SV (LT, LP and Union-Rem-CAS with SPLICE_ATOMIC return
+ * GCONN_EUNSUPPORTED). */
 gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t* fv,
                                    uint32_t* labels_out, void* workspace, size_t workspace_bytes,
                                    const gconn_options* opt, gconn_stats* stats, void* stream);
@@ -205,6 +211,16 @@ gconn_status gconn_inc_insert_batch(gconn_inc* h, const uint32_t* src, const uin
 /* out[i] (device, q bytes) = 1 iff a[i] and b[i] are connected, else 0. */
 gconn_status gconn_inc_query_batch(gconn_inc* h, const uint32_t* a, const uint32_t* b, uint64_t q,
                                    uint8_t* out, void* stream);
+/* Mixed batch (Alg. "GConn for Incremental Connectivity": a batch mixes
+ * inserts and queries).  kind[i] (device, count bytes) is GCONN_REQ_INSERT for
+ * the edge (a[i], b[i]) and GCONN_REQ_QUERY for the pair (a[i], b[i]).  Every
+ * insert of the batch is applied first, then every query is answered, so the
+ * answers are deterministic: out[i] (device, count bytes) = 1 iff element i is
+ * a query whose endpoints are connected once all of the batch's inserts (and
+ * the earlier batches) are in; 0 for inserts.  Any other kind value is
+ * GCONN_EINVAL when options.validate is set, and undefined otherwise. */
+gconn_status gconn_inc_mixed_batch(gconn_inc* h, const uint8_t* kind, const uint32_t* a,
+                                   const uint32_t* b, uint64_t count, uint8_t* out, void* stream);
 /* labels_out (device, n_max entries) = canonical labels of the current graph. */
 gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream);
 /* Frees the host handle only (no device memory is owned). */

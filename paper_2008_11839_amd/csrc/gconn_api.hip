@@ -39,7 +39,7 @@ gconn_status check_options(const gconn_options& o) {
     return fail(GCONN_EINVAL, "options.link out of range");
   if (o.find < GCONN_FIND_NAIVE || o.find > GCONN_FIND_COMPRESS)
     return fail(GCONN_EINVAL, "options.find out of range");
-  if (o.splice < GCONN_SPLICE_SPLIT_ONE || o.splice > GCONN_SPLICE_HALVE_ONE)
+  if (o.splice < GCONN_SPLICE_SPLIT_ONE || o.splice > GCONN_SPLICE_ATOMIC)
     return fail(GCONN_EINVAL, "options.splice out of range");
   if (o.lt_variant < 0 || o.lt_variant >= GCONN_LT_COUNT)
     return fail(GCONN_EINVAL, "options.lt_variant out of range");
@@ -204,6 +204,10 @@ gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t*
   if (o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP)
     return fail(GCONN_EUNSUPPORTED,
                 "spanning forest needs a root-based finish: a union-find rule or SV");
+  if (o.link == GCONN_LINK_REM_CAS && o.splice == GCONN_SPLICE_ATOMIC)
+    return fail(GCONN_EUNSUPPORTED,
+                "spanning forests need root-based links; Rem's splice re-hangs non-roots "
+                "without an edge to record");
   GCONN_TRY(check_device_ready());
   GCONN_TRY(check_graph(g));
   if (g->format == GCONN_COO) o.sample = GCONN_SAMPLE_NONE;
@@ -307,6 +311,23 @@ gconn_status gconn_inc_query_batch(gconn_inc* h, const uint32_t* a, const uint32
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (h->opt.validate) GCONN_TRY(validate_ids(h, a, b, q, s));
   return launch_query(h->opt, h->P, a, b, q, out, s);
+}
+
+gconn_status gconn_inc_mixed_batch(gconn_inc* h, const uint8_t* kind, const uint32_t* a,
+                                   const uint32_t* b, uint64_t count, uint8_t* out, void* stream) {
+  clear_error();
+  if (!h) return fail(GCONN_EINVAL, "handle is NULL");
+  if (count == 0) return GCONN_OK;
+  GCONN_TRY(check_device_ptr(kind, "kind"));
+  GCONN_TRY(check_device_ptr(a, "a"));
+  GCONN_TRY(check_device_ptr(b, "b"));
+  GCONN_TRY(check_device_ptr(out, "out"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->opt.validate) {
+    GCONN_TRY(validate_ids(h, a, b, count, s));
+    GCONN_TRY(validate_kinds(kind, count, reinterpret_cast<Ctrl*>(h->ws), s));
+  }
+  return launch_mixed(h->opt, h->P, h->H, kind, a, b, count, out, s);
 }
 
 gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream) {

@@ -136,6 +136,12 @@ gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, ui
                             Ctrl* ctrl, hipStream_t s);
 gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a,
                           const uint32_t* b, uint64_t q, uint8_t* out, hipStream_t s);
+// Mixed batch: the inserts (kind 0), then the queries (kind 1; out 0 for inserts).
+gconn_status launch_mixed(const gconn_options& o, uint32_t* P, uint32_t* H, const uint8_t* kind,
+                          const uint32_t* a, const uint32_t* b, uint64_t count, uint8_t* out,
+                          hipStream_t s);
+// Synchronous check that every kind is 0 or 1; uses ctrl as scratch.
+gconn_status validate_kinds(const uint8_t* kind, uint64_t count, Ctrl* ctrl, hipStream_t s);
 
 // Phase profiler (thread-local; HIP events on the caller's stream).
 enum Phase : int {

@@ -54,7 +54,7 @@ namespace gconn {
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 enum FindRule : int { kFindNaive = 0, kFindSplit = 1, kFindHalve = 2, kFindCompress = 3 };
-enum SpliceRule : int { kSpliceSplitOne = 0, kSpliceHalveOne = 1 };
+enum SpliceRule : int { kSpliceSplitOne = 0, kSpliceHalveOne = 1, kSpliceAtomic = 2 };
 enum UnionRule : int { kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnionRemCas = 3 };
 
 // Wavefront scope compiles to an ordinary cached global load (measured fastest
@@ -308,6 +308,45 @@ GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
   }
 }
 
+// Union-Rem-CAS with Rem's own splice (SpliceAtomic, Appendix A.2): while the
+// two current nodes have different parents, the one with the larger parent is
+// either a root (CAS it under the other parent) or is re-hung under the other
+// node's parent by a CAS, and the walk moves on to its old parent, whose side
+// of the union is still pending.  A splice moves a node out of its ancestors'
+// path, so the carried-value shortcuts of union_rem_cas do not apply: both
+// parents are re-read, device-coherently, on every iteration, and a failed
+// CAS only means the next iteration sees the new parent.
+template <int F>
+GCONN_HD bool union_rem_splice(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t ru = u, rv = v;
+  for (;;) {
+    uint32_t pru = ld_agent(&c.P[ru]), prv = ld_agent(&c.P[rv]);
+    if (pru == prv) return false;
+    if (pru < prv) {
+      uint32_t t = ru;
+      ru = rv;
+      rv = t;
+      t = pru;
+      pru = prv;
+      prv = t;
+    }
+    uint32_t e = pru;
+    if (ru == pru) {
+      if (cas(&c.P[ru], e, prv)) {
+        record_link(c, ru, u, v);
+        if constexpr (F != kFindNaive) {
+          find<F>(c.P, u, true);
+          find<F>(c.P, v, true);
+        }
+        return true;
+      }
+      continue;
+    }
+    cas(&c.P[ru], e, prv);  // splice; on failure P[ru] moved and is re-read next time
+    ru = pru;
+  }
+}
+
 // Compile-time rule bundle.
 template <int U, int F, int S>
 struct Rule {
@@ -316,6 +355,7 @@ struct Rule {
     if constexpr (U == kUnionAsync) return union_async<F>(c, u, v);
     else if constexpr (U == kUnionHooks) return union_hooks<F>(c, u, v);
     else if constexpr (U == kUnionEarly) return union_early<F>(c, u, v);
+    else if constexpr (S == kSpliceAtomic) return union_rem_splice<F>(c, u, v);
     else return union_rem_cas<F, S>(c, u, v);
   }
 };

@@ -1125,6 +1125,33 @@ __global__ void k_query(const uint32_t* __restrict__ a, const uint32_t* __restri
   }
 }
 
+// Mixed batches (the paper's incremental batches mix inserts and queries): all
+// inserts of the batch first, then every query, so the answers do not depend
+// on how the two interleave on the device.
+template <class R>
+__global__ void k_unite_kind(const uint8_t* __restrict__ kind, const uint32_t* __restrict__ a,
+                             const uint32_t* __restrict__ b, uint64_t m, LinkCtx lc) {
+  for (uint64_t e = gtid(); e < m; e += wave_stride())
+    if (kind[e] == GCONN_REQ_INSERT) R::unite(lc, a[e], b[e]);
+}
+
+template <class R>
+__global__ void k_query_kind(const uint8_t* __restrict__ kind, const uint32_t* __restrict__ a,
+                             const uint32_t* __restrict__ b, uint64_t q, uint32_t* P,
+                             uint8_t* out, int ac) {
+  for (uint64_t i = gtid(); i < q; i += wave_stride()) {
+    uint8_t r = 0;
+    if (kind[i] == GCONN_REQ_QUERY)
+      r = (uint8_t)(find<R::kFind>(P, a[i], ac != 0) == find<R::kFind>(P, b[i], ac != 0));
+    out[i] = r;
+  }
+}
+
+__global__ void k_validate_kinds(const uint8_t* kind, uint64_t m, Ctrl* c) {
+  for (uint64_t e = gtid(); e < m; e += wave_stride())
+    if (kind[e] > GCONN_REQ_QUERY) c->err = 1;
+}
+
 // =============================================================== host side
 namespace {
 
@@ -1162,6 +1189,13 @@ gconn_status with_rule(int link, int find_rule, int splice, Fn&& fn) {
         default: return fn(Rule<kUnionEarly, kFindCompress, 0>{});
       }
     case GCONN_LINK_REM_CAS:
+      if (splice == kSpliceAtomic) {
+        switch (find_rule) {
+          case kFindNaive: return fn(Rule<kUnionRemCas, kFindNaive, kSpliceAtomic>{});
+          case kFindSplit: return fn(Rule<kUnionRemCas, kFindSplit, kSpliceAtomic>{});
+          default: return fn(Rule<kUnionRemCas, kFindHalve, kSpliceAtomic>{});
+        }
+      }
       if (splice == kSpliceSplitOne) {
         switch (find_rule) {
           case kFindNaive: return fn(Rule<kUnionRemCas, kFindNaive, kSpliceSplitOne>{});
@@ -1233,7 +1267,10 @@ struct Run {
     c.fu = fu;
     c.fv = fv;
     c.hooks = want_stats ? &ctrl->stat_hooks : nullptr;
-    c.atomic_compress = (uint32_t)o.atomic_compress;
+    // Rem's splice moves a node out of its ancestors' paths, so the writes
+    // that compress next to it stay CASes.
+    c.atomic_compress = (o.splice == GCONN_SPLICE_ATOMIC && o.link == GCONN_LINK_REM_CAS)
+                            ? 1u : (uint32_t)o.atomic_compress;
     return c;
   }
 
@@ -1245,7 +1282,8 @@ struct Run {
 
   // Union-Rem-CAS first-k sampling as a step machine (uint32 offsets only).
   bool kout_step_machine() const {
-    return o.link == GCONN_LINK_REM_CAS && !o.kout_random && !g.offsets_64 && o.schedule == 2;
+    return o.link == GCONN_LINK_REM_CAS && o.splice != GCONN_SPLICE_ATOMIC && !o.kout_random &&
+           !g.offsets_64 && o.schedule == 2;
   }
 
   template <typename OffT>
@@ -1534,7 +1572,8 @@ gconn_status launch_insert(const gconn_options& o, uint32_t* P, uint32_t* H, con
   c.H = H;
   c.fu = c.fv = nullptr;
   c.hooks = nullptr;
-  c.atomic_compress = (uint32_t)o.atomic_compress;
+  c.atomic_compress = (o.splice == GCONN_SPLICE_ATOMIC && o.link == GCONN_LINK_REM_CAS)
+                          ? 1u : (uint32_t)o.atomic_compress;
   const uint32_t block = (uint32_t)o.block;
   return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
     using R = decltype(rule);
@@ -1637,6 +1676,42 @@ gconn_status profile_read(gconn_phase_times* out, int reset) {
     for (double& a : g_prof.acc) a = 0;
     g_prof.runs = 0;
   }
+  return GCONN_OK;
+}
+
+gconn_status launch_mixed(const gconn_options& o, uint32_t* P, uint32_t* H, const uint8_t* kind,
+                          const uint32_t* a, const uint32_t* b, uint64_t count, uint8_t* out,
+                          hipStream_t s) {
+  if (count == 0) return GCONN_OK;
+  LinkCtx c;
+  c.P = P;
+  c.H = H;
+  c.fu = c.fv = nullptr;
+  c.hooks = nullptr;
+  c.atomic_compress = (o.splice == GCONN_SPLICE_ATOMIC && o.link == GCONN_LINK_REM_CAS)
+                          ? 1u : (uint32_t)o.atomic_compress;
+  const uint32_t block = (uint32_t)o.block;
+  return with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+    using R = decltype(rule);
+    k_unite_kind<R><<<grid_for(count, block), block, 0, s>>>(kind, a, b, count, c);
+    GCONN_LAUNCHED("k_unite_kind");
+    k_query_kind<R><<<grid_for(count, block), block, 0, s>>>(kind, a, b, count, P, out,
+                                                            (int)c.atomic_compress);
+    GCONN_LAUNCHED("k_query_kind");
+    return GCONN_OK;
+  });
+}
+
+gconn_status validate_kinds(const uint8_t* kind, uint64_t count, Ctrl* ctrl, hipStream_t s) {
+  if (count == 0) return GCONN_OK;
+  k_ctrl_init<<<1, 256, 0, s>>>(ctrl);
+  GCONN_LAUNCHED("k_ctrl_init");
+  k_validate_kinds<<<grid_for(count, 256), 256, 0, s>>>(kind, count, ctrl);
+  GCONN_LAUNCHED("k_validate_kinds");
+  uint32_t err = 0;
+  GCONN_HIP(hipMemcpyAsync(&err, &ctrl->err, sizeof(err), hipMemcpyDeviceToHost, s));
+  GCONN_HIP(hipStreamSynchronize(s));
+  if (err) return fail(GCONN_EINVAL, "mixed batch: a kind other than insert (0) or query (1)");
   return GCONN_OK;
 }
 

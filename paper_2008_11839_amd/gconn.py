@@ -21,7 +21,7 @@ EMPTY = 0xFFFFFFFF
 SAMPLE = {"none": 0, "kout": 1, "hb": 2, "bfs": 3}
 LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt": 6, "lp": 7}
 FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3}
-SPLICE = {"split_one": 0, "halve_one": 1}
+SPLICE = {"split_one": 0, "halve_one": 1, "splice_atomic": 2}
 SCHEDULE = {"auto": 0, "lane": 1, "step": 2}
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
                "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]
@@ -92,7 +92,7 @@ EXPORTS = ["gconn_server_create", "gconn_server_submit", "gconn_server_wait",
            "gconn_server_drain", "gconn_server_destroy", "gconn_cc_batch_workspace_size", "gconn_cc_batch", "gconn_autotune",
            "gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
-           "gconn_inc_query_batch", "gconn_inc_labels", "gconn_inc_destroy",
+           "gconn_inc_query_batch", "gconn_inc_mixed_batch", "gconn_inc_labels", "gconn_inc_destroy",
            "gconn_status_string", "gconn_last_error", "gconn_version"]
 
 _lib = None
@@ -125,6 +125,8 @@ def lib() -> ctypes.CDLL:
         L.gconn_inc_insert_batch.argtypes = [vp, vp, vp, ctypes.c_uint64, vp]
         L.gconn_inc_query_batch.restype = ctypes.c_int
         L.gconn_inc_query_batch.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp]
+        L.gconn_inc_mixed_batch.restype = ctypes.c_int
+        L.gconn_inc_mixed_batch.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp, vp]
         L.gconn_inc_labels.restype = ctypes.c_int
         L.gconn_inc_labels.argtypes = [vp, vp, vp]
         L.gconn_inc_destroy.restype = ctypes.c_int
@@ -356,6 +358,18 @@ class Incremental:
         if out is None:
             out = torch.empty(max(a.numel(), 1), dtype=torch.uint8, device=a.device)[: a.numel()]
         _check(lib().gconn_inc_query_batch(self._h, _ptr(a), _ptr(b), a.numel(),
+                                           _ptr(out) if a.numel() else None, _stream(stream)))
+        return out
+
+    def mixed(self, kind: torch.Tensor, a: torch.Tensor, b: torch.Tensor,
+              out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Mixed batch: kind (uint8, 0 insert / 1 query); the batch's inserts are
+        applied first, then out[i] = 1 iff query i's endpoints are connected."""
+        if kind.dtype != torch.uint8:
+            raise ValueError("kind must be uint8")
+        if out is None:
+            out = torch.empty(max(a.numel(), 1), dtype=torch.uint8, device=a.device)[: a.numel()]
+        _check(lib().gconn_inc_mixed_batch(self._h, _ptr(kind), _ptr(a), _ptr(b), a.numel(),
                                            _ptr(out) if a.numel() else None, _stream(stream)))
         return out
 

@@ -4,7 +4,8 @@
 //
 //   rules_stress <edges.bin> <n> <rule> <threads> <labels.out> [atomic_compress]
 // edges.bin: uint32 pairs; rule: 0-3 Async (naive/split/halve/compress),
-// 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one).
+// 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one),
+// 18-20 Rem-CAS with Rem's splice (naive/split/halve).
 // Writes labels (root of every vertex, uint32) and prints the hook count.
 #include <hip/hip_runtime.h>
 
@@ -67,6 +68,9 @@ int main(int argc, char** argv) {
     case 15: run<Rule<kUnionRemCas, kFindNaive, kSpliceHalveOne>>(e, c, threads); break;
     case 16: run<Rule<kUnionRemCas, kFindSplit, kSpliceHalveOne>>(e, c, threads); break;
     case 17: run<Rule<kUnionRemCas, kFindHalve, kSpliceHalveOne>>(e, c, threads); break;
+    case 18: c.atomic_compress = 1; run<Rule<kUnionRemCas, kFindNaive, kSpliceAtomic>>(e, c, threads); break;
+    case 19: c.atomic_compress = 1; run<Rule<kUnionRemCas, kFindSplit, kSpliceAtomic>>(e, c, threads); break;
+    case 20: c.atomic_compress = 1; run<Rule<kUnionRemCas, kFindHalve, kSpliceAtomic>>(e, c, threads); break;
     default: return 5;
   }
   std::vector<uint32_t> lab(n);

@@ -18,6 +18,8 @@ CONFIGS = [dict(sample=s, link=l, find=f, splice=sp)
            for s, l, f, sp in [("kout", "rem_cas", "split", "split_one"),
                                ("kout", "rem_cas", "naive", "split_one"),
                                ("kout", "rem_cas", "halve", "halve_one"),
+                               ("kout", "rem_cas", "split", "splice_atomic"),
+                               ("none", "rem_cas", "halve", "splice_atomic"),
                                ("kout", "async", "split", "split_one"),
                                ("kout", "early", "halve", "split_one"),
                                ("kout", "hooks", "split", "split_one"),

@@ -22,7 +22,7 @@ UF_RULES = ([("async", f, "split_one") for f in ("naive", "split", "halve", "com
             + [("hooks", f, "split_one") for f in ("naive", "split", "halve", "compress")]
             + [("early", f, "split_one") for f in ("naive", "split", "halve", "compress")]
             + [("rem_cas", f, s) for f in ("naive", "split", "halve")
-               for s in ("split_one", "halve_one")]
+               for s in ("split_one", "halve_one", "splice_atomic")]
             + [("ecl", "halve", "split_one")])
 SAMPLERS = ["none", "kout", "hb", "bfs"]
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
@@ -118,7 +118,11 @@ def test_liu_tarjan_variants(cases, variant):
 def test_spanning_forest_valid_and_slot_exact(cases):
     import torch
     from paper_2008_11839_amd import gconn as G
-    rules = UF_RULES + [("sv", "split", "split_one")]
+    rules = [r for r in UF_RULES if r[2] != "splice_atomic"] + [("sv", "split", "split_one")]
+    C, dg, _ = cases["er"]
+    with pytest.raises(G.GconnError) as e:  # Rem's splice links non-roots: no forest
+        G.spanning_forest(dg, options=G.Options(link="rem_cas", splice="splice_atomic"))
+    assert e.value.status == -7
     for name, (C, dg, want) in cases.items():
         roots_mask = want != np.arange(C.n, dtype=np.uint32)
         for sample in SAMPLERS:
@@ -388,6 +392,7 @@ def test_kout_prelink(cases):
                         assert st["active_vertices"] == oracle.active_count(C.n, C.offsets, s_lab, L)
                     if link not in ("sv", "ecl"):
                         assert st["hooks"] == C.n - c, (name, k, link)
+                    if link not in ("sv", "ecl") and splice != "splice_atomic":
                         fu, fv, _ = G.spanning_forest(dg, want_labels=False, options=o)
                         torch.cuda.synchronize()
                         fu, fv = G.to_u32(fu), G.to_u32(fv)
@@ -396,3 +401,57 @@ def test_kout_prelink(cases):
         for k, random in ((3, False), (2, True)):
             got = _labels(G, dg, sample="kout", k=k, kout_random=random, kout_prelink=True)
             assert np.array_equal(got, want), (name, k, random)
+
+
+@pytest.mark.parametrize("ratio", [1.0, 0.25, 8.0])
+def test_incremental_mixed_batches_match_oracle(ratio):
+    """Mixed insert/query batches (inserts of a batch first, then its queries):
+    every answer equals the oracle's after every batch, for every root-based
+    union rule, on an RMAT edge stream and on a Barabasi-Albert stream."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    n = 20000
+    streams = {"rmat": graphgen.rmat_edges(15, 40000, 31, n=n),
+               "ba": graphgen.ba_edges(n, 3, 32)}
+    for sname, (src, dst) in streams.items():
+        if sname == "rmat":
+            graphgen.shuffle_edges(src, dst, 31)
+        kind, a, b = graphgen.mixed_stream(src, dst, n, ratio, 33)
+        bounds = [0, 1, 17, 5000, 5001, 30000, len(kind)]
+        rules = UF_RULES if ratio == 1.0 else UF_RULES[::4]
+        for link, find, splice in rules:
+            say(f"[mixed] stream={sname} ratio={ratio} link={link} find={find} splice={splice}")
+            inc = G.Incremental(n, options=G.Options(sample="none", link=link, find=find,
+                                                     splice=splice))
+            uf = oracle.UnionFind(n)
+            for i in range(len(bounds) - 1):
+                lo, hi = bounds[i], bounds[i + 1]
+                kk, aa, bb = kind[lo:hi], a[lo:hi], b[lo:hi]
+                ins = kk == 0
+                uf.insert(aa[ins], bb[ins])
+                want = np.zeros(hi - lo, np.uint8)
+                want[~ins] = uf.query(aa[~ins], bb[~ins])
+                out = inc.mixed(torch.from_numpy(kk).cuda(),
+                                torch.from_numpy(aa.view(np.int32)).cuda(),
+                                torch.from_numpy(bb.view(np.int32)).cuda())
+                got = out.cpu().numpy()
+                assert np.array_equal(got, want), (sname, ratio, link, find, splice, i)
+            inc.close()
+
+
+def test_incremental_mixed_validation():
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    inc = G.Incremental(10, options=G.Options(sample="none", validate=True))
+    k = torch.tensor([0, 2], dtype=torch.uint8, device="cuda")
+    a = torch.tensor([1, 2], dtype=torch.int32, device="cuda")
+    with pytest.raises(G.GconnError):
+        inc.mixed(k, a, a)
+    with pytest.raises(G.GconnError):
+        inc.mixed(torch.tensor([0, 1], dtype=torch.uint8, device="cuda"), a,
+                  torch.tensor([1, 12], dtype=torch.int32, device="cuda"))
+    out = inc.mixed(torch.tensor([0, 1, 1], dtype=torch.uint8, device="cuda"),
+                    torch.tensor([1, 1, 3], dtype=torch.int32, device="cuda"),
+                    torch.tensor([2, 2, 4], dtype=torch.int32, device="cuda"))
+    assert out.cpu().tolist() == [0, 1, 0]
+    inc.close()

@@ -114,3 +114,35 @@ def test_batched_specs_ranges():
     assert 800 < kinds.count("rmat") < 1200
     # log-uniform: median near 10^4.5
     assert 10 ** 4.3 < np.median(ns) < 10 ** 4.7
+
+
+def test_barabasi_albert_stream():
+    n, k = 50000, 10
+    s, d = graphgen.ba_edges(n, k, 3)
+    s2, d2 = graphgen.ba_edges(n, k, 3)
+    assert np.array_equal(s, s2) and np.array_equal(d, d2)
+    # arrival order, k slots per vertex, every kept edge points to an earlier vertex
+    assert np.all(np.diff(s.astype(np.int64)) >= 0)
+    assert np.all(d < s)
+    assert np.bincount(s, minlength=n).max() <= k
+    # self-loops (dropped): slot e copies itself with probability 1/(2e+1),
+    # about ln(2nk)/2 ~ 7 in total; allow generous slack
+    assert n * k - len(s) < 60
+    # preferential attachment: heavy tail (max degree far above the mean 2k)
+    deg = np.bincount(np.concatenate([s, d]), minlength=n)
+    assert deg.max() > 40 * 2 * k
+    assert abs(deg.mean() - 2 * k * len(s) / (n * k)) < 1e-9
+    # vertex 0 arrives first: its k slots can only point at itself
+    assert 0 not in set(s.tolist())
+
+
+def test_mixed_stream_composition():
+    src, dst = graphgen.rmat_edges(12, 5000, 4)
+    for ratio in (1.0, 4.0, 0.5):
+        kind, a, b = graphgen.mixed_stream(src, dst, 1 << 12, ratio, 9)
+        q = int(round(len(src) / ratio))
+        assert len(kind) == len(src) + q and int(kind.sum()) == q
+        ins = kind == 0
+        got = sorted(zip(a[ins].tolist(), b[ins].tolist()))
+        assert got == sorted(zip(src.tolist(), dst.tolist()))
+        assert a.max() < (1 << 12) and b.max() < (1 << 12)

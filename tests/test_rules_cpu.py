@@ -16,7 +16,7 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "native", "rules_stress.hip")
 BIN = os.path.join(ROOT, "_build", "tests", "rules_stress")
-RULES = list(range(18))
+RULES = list(range(21))
 
 
 @pytest.fixture(scope="module")
@@ -36,6 +36,9 @@ def harness():
 def _graphs():
     yield "star_max", 3000, np.array([[2999, v] for v in range(2999)], np.uint32)
     yield "path_desc", 2000, np.array([[i + 1, i] for i in range(1999)][::-1], np.uint32)
+    perm = np.random.default_rng(5).permutation(3000).astype(np.uint32)
+    path = np.stack([perm[:-1], perm[1:]], 1)
+    yield "path_shuffled", 3000, path[np.random.default_rng(6).permutation(len(path))]
     s, d = graphgen.rmat_edges(13, 80000, 4)
     yield "rmat13", 1 << 13, np.stack([s, d], 1)
     s, d = graphgen.er_edges(20000, 30000, 5)
