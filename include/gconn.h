@@ -73,7 +73,13 @@ enum {
                              full-compress pass                                    */
   GCONN_LINK_SV = 5,      /* root-based Shiloach-Vishkin (writeMin + full shortcut) */
   GCONN_LINK_LT = 6,      /* Liu-Tarjan rule set, variant in lt_variant            */
-  GCONN_LINK_LP = 7       /* label propagation                                     */
+  GCONN_LINK_LP = 7,      /* label propagation                                     */
+  GCONN_LINK_AFFOREST = 8, /* G_Afforest: Afforest's link (walk two levels, CAS a
+                             root under the lower side), separate full compress   */
+  GCONN_LINK_REM_LOCK = 9 /* Union-Rem-Lock: Rem's algorithm, the root link made
+                             under a per-vertex try-lock (wave-safe: a lane that
+                             gets the lock finishes and releases it in the same
+                             step, so lanes of one wave never wait on each other) */
 };
 
 /* On-the-fly compression inside Find (Appendix A.2, find options). */
@@ -184,8 +190,8 @@ gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspac
  * edge that linked it; other slots hold 0xFFFFFFFF.  Exactly n - c slots are
  * filled (c = number of components).  labels_out (device, nullable) receives
  * the canonical labels as in gconn_cc.  Root-based finishes only: union-find
- * rules and SV (LT, LP and Union-Rem-CAS with SPLICE_ATOMIC return
- * GCONN_EUNSUPPORTED). */
+ * rules and SV (LT, LP, and Union-Rem-CAS / Rem-Lock with SPLICE_ATOMIC
+ * return GCONN_EUNSUPPORTED). */
 gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t* fv,
                                    uint32_t* labels_out, void* workspace, size_t workspace_bytes,
                                    const gconn_options* opt, gconn_stats* stats, void* stream);

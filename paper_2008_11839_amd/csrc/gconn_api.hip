@@ -29,13 +29,14 @@ gconn_status hip_fail(hipError_t e, const char* what) {
 
 bool is_union_find(int link) {
   return link == GCONN_LINK_ASYNC || link == GCONN_LINK_HOOKS || link == GCONN_LINK_EARLY ||
-         link == GCONN_LINK_REM_CAS || link == GCONN_LINK_ECL;
+         link == GCONN_LINK_REM_CAS || link == GCONN_LINK_ECL || link == GCONN_LINK_AFFOREST ||
+         link == GCONN_LINK_REM_LOCK;
 }
 
 gconn_status check_options(const gconn_options& o) {
   if (o.sample < GCONN_SAMPLE_NONE || o.sample > GCONN_SAMPLE_BFS)
     return fail(GCONN_EINVAL, "options.sample out of range");
-  if (o.link < GCONN_LINK_ASYNC || o.link > GCONN_LINK_LP)
+  if (o.link < GCONN_LINK_ASYNC || o.link > GCONN_LINK_REM_LOCK)
     return fail(GCONN_EINVAL, "options.link out of range");
   if (o.find < GCONN_FIND_NAIVE || o.find > GCONN_FIND_COMPRESS)
     return fail(GCONN_EINVAL, "options.find out of range");
@@ -43,9 +44,10 @@ gconn_status check_options(const gconn_options& o) {
     return fail(GCONN_EINVAL, "options.splice out of range");
   if (o.lt_variant < 0 || o.lt_variant >= GCONN_LT_COUNT)
     return fail(GCONN_EINVAL, "options.lt_variant out of range");
-  if (o.link == GCONN_LINK_REM_CAS && o.find == GCONN_FIND_COMPRESS)
+  if ((o.link == GCONN_LINK_REM_CAS || o.link == GCONN_LINK_REM_LOCK) &&
+      o.find == GCONN_FIND_COMPRESS)
     return fail(GCONN_EUNSUPPORTED,
-                "Union-Rem-CAS combines with FindNaive, FindSplit or FindHalve only");
+                "Union-Rem-CAS / Rem-Lock combine with FindNaive, FindSplit or FindHalve only");
   if (o.k < 1 || o.k > 64) return fail(GCONN_EINVAL, "options.k must be in [1, 64]");
   if (o.hb_n < 1 || o.hb_n > 1024) return fail(GCONN_EINVAL, "options.hb_n must be in [1, 1024]");
   if (o.lmax_samples < 1 || o.lmax_samples > kMaxLmaxSamples)
@@ -204,7 +206,8 @@ gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t*
   if (o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP)
     return fail(GCONN_EUNSUPPORTED,
                 "spanning forest needs a root-based finish: a union-find rule or SV");
-  if (o.link == GCONN_LINK_REM_CAS && o.splice == GCONN_SPLICE_ATOMIC)
+  if ((o.link == GCONN_LINK_REM_CAS || o.link == GCONN_LINK_REM_LOCK) &&
+      o.splice == GCONN_SPLICE_ATOMIC)
     return fail(GCONN_EUNSUPPORTED,
                 "spanning forests need root-based links; Rem's splice re-hangs non-roots "
                 "without an edge to record");
@@ -231,7 +234,7 @@ gconn_status gconn_inc_workspace_size(uint32_t n_max, const gconn_graph* initial
   gconn_options o;
   GCONN_TRY(resolve_options(opt, &o));
   size_t total = align_up(sizeof(Ctrl), 256);
-  if (o.link == GCONN_LINK_HOOKS) total += align_up(4ull * n_max + 1, 256);
+  if (needs_claims(o.link)) total += align_up(4ull * n_max + 1, 256);
   if (initial) total += plan_workspace(*initial, o, false, true).total;
   *bytes = total;
   return GCONN_OK;
@@ -261,7 +264,7 @@ gconn_status gconn_inc_create(uint32_t n_max, uint32_t* parent_buf, const gconn_
   uint8_t* ws = static_cast<uint8_t*>(workspace);
   size_t at = align_up(sizeof(Ctrl), 256);
   uint32_t* H = nullptr;
-  if (o.link == GCONN_LINK_HOOKS) {
+  if (needs_claims(o.link)) {
     H = reinterpret_cast<uint32_t*>(ws + at);
     at += align_up(4ull * n_max + 1, 256);
   }

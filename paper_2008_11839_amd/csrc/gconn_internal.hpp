@@ -72,6 +72,12 @@ struct WsLayout {
   size_t total = 0;
 };
 
+// Rules that need a per-vertex claim array (LinkCtx::H, kEmpty-filled):
+// Union-Hooks' hooks and Union-Rem-Lock's locks.
+inline bool needs_claims(int link) {
+  return link == GCONN_LINK_HOOKS || link == GCONN_LINK_REM_LOCK;
+}
+
 // Thread-local error reporting.
 void set_error(const std::string& msg);
 void clear_error();

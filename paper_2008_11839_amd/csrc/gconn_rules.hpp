@@ -55,7 +55,10 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 enum FindRule : int { kFindNaive = 0, kFindSplit = 1, kFindHalve = 2, kFindCompress = 3 };
 enum SpliceRule : int { kSpliceSplitOne = 0, kSpliceHalveOne = 1, kSpliceAtomic = 2 };
-enum UnionRule : int { kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnionRemCas = 3 };
+enum UnionRule : int {
+  kUnionAsync = 0, kUnionHooks = 1, kUnionEarly = 2, kUnionRemCas = 3, kUnionAfforest = 4,
+  kUnionRemLock = 5
+};
 
 // Wavefront scope compiles to an ordinary cached global load (measured fastest
 // for the union-find kernels on MI355X; see the memory-model note above).
@@ -347,6 +350,91 @@ GCONN_HD bool union_rem_splice(const LinkCtx& c, uint32_t u, uint32_t v) {
   }
 }
 
+// G_Afforest's link (the finish of Afforest, Sutton et al. 2018, brought into
+// the framework; Related Work and the state-of-the-art comparison): compare
+// the parents of the two endpoints; when they differ, the higher one either
+// already points at the lower (done), or is a root and is CASed under the
+// lower, or both sides move up (the higher side by two levels).  No path
+// compression happens here: a separate full compress pass follows.  Every
+// iteration lowers the larger of the two values compared, so it terminates.
+GCONN_HD bool union_afforest(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t p1 = ld(&c.P[u]), p2 = ld(&c.P[v]);
+  while (p1 != p2) {
+    const uint32_t high = p1 > p2 ? p1 : p2, low = p1 > p2 ? p2 : p1;
+    const uint32_t ph = ld(&c.P[high]);
+    if (ph == low) return false;
+    if (ph == high) {
+      uint32_t e = high;
+      if (cas(&c.P[high], e, low)) {
+        record_link(c, high, u, v);
+        return true;
+      }
+    }
+    p1 = ld(&c.P[ld(&c.P[high])]);
+    p2 = ld(&c.P[low]);
+  }
+  return false;
+}
+
+// Union-Rem-Lock (Appendix A.2, after Patwary et al.): Rem's walk, the link of
+// a root made under a lock on that root.  GPU lanes of one wave run in
+// lockstep, so a lane spinning on a lock held by another lane of its wave
+// would never let the holder run: the lock is only ever tried, and a lane that
+// gets it does the guarded check-and-link and releases it in the same step;
+// a lane that does not get it re-reads and tries again.  The lock array is
+// LinkCtx::H (kEmpty = free).  As printed the procedure returns after the
+// critical section whether or not the link happened; a failed check (the root
+// was linked meanwhile) continues the walk instead.  Compression runs when the
+// walk ends without a link, as in the listing.
+template <int F, int S>
+GCONN_HD bool union_rem_lock(const LinkCtx& c, uint32_t u, uint32_t v) {
+  uint32_t ru = u, rv = v;
+  for (;;) {
+    uint32_t pru = ld_agent(&c.P[ru]), prv = ld_agent(&c.P[rv]);
+    if (pru == prv) break;
+    if (pru < prv) {
+      uint32_t t = ru;
+      ru = rv;
+      rv = t;
+      t = pru;
+      pru = prv;
+      prv = t;
+    }
+    if (ru == pru) {
+      uint32_t lk = kEmpty;
+      if (__hip_atomic_compare_exchange_strong(&c.H[ru], &lk, 0u, __ATOMIC_ACQUIRE,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        const uint32_t pv = ld_agent(&c.P[rv]);
+        const bool ok = ld_agent(&c.P[ru]) == ru && ru > pv;
+        if (ok) st(&c.P[ru], pv);
+        __hip_atomic_store(&c.H[ru], kEmpty, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (ok) {
+          record_link(c, ru, u, v);
+          return true;
+        }
+      }
+      continue;
+    }
+    if constexpr (S == kSpliceAtomic) {
+      uint32_t e = pru;
+      cas(&c.P[ru], e, prv);
+      ru = pru;
+    } else {
+      const uint32_t w = ld_agent(&c.P[pru]);
+      if (w != pru) {
+        uint32_t e = pru;
+        cas(&c.P[ru], e, w);
+      }
+      ru = (S == kSpliceSplitOne) ? pru : w;
+    }
+  }
+  if constexpr (F != kFindNaive) {
+    find<F>(c.P, u, true);
+    find<F>(c.P, v, true);
+  }
+  return false;
+}
+
 // Compile-time rule bundle.
 template <int U, int F, int S>
 struct Rule {
@@ -355,6 +443,8 @@ struct Rule {
     if constexpr (U == kUnionAsync) return union_async<F>(c, u, v);
     else if constexpr (U == kUnionHooks) return union_hooks<F>(c, u, v);
     else if constexpr (U == kUnionEarly) return union_early<F>(c, u, v);
+    else if constexpr (U == kUnionAfforest) return union_afforest(c, u, v);
+    else if constexpr (U == kUnionRemLock) return union_rem_lock<F, S>(c, u, v);
     else if constexpr (S == kSpliceAtomic) return union_rem_splice<F>(c, u, v);
     else return union_rem_cas<F, S>(c, u, v);
   }

@@ -247,9 +247,10 @@ gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* paren
   if (!cfg || !out) return fail(GCONN_EINVAL, "cfg and out are required");
   *out = nullptr;
   GCONN_TRY(check_options(cfg->options));
-  if (!is_union_find(cfg->options.link) || cfg->options.link == GCONN_LINK_HOOKS)
+  if (!is_union_find(cfg->options.link) || needs_claims(cfg->options.link))
     return fail(GCONN_EUNSUPPORTED,
-                "the server runs Union-Async, Union-Early, Union-Rem-CAS or ECL-CC's rule");
+                "the server runs Union-Async, Union-Early, Union-Rem-CAS, ECL-CC's rule or "
+                "G_Afforest's link");
   if (cfg->n_max == 0 || cfg->n_max > 0xFFFFFFFEu) return fail(GCONN_EINVAL, "n_max out of range");
   if (cfg->streams > 16) return fail(GCONN_EINVAL, "streams must be 1..16");
   if (cfg->arena_bytes < kGranule) return fail(GCONN_EINVAL, "arena too small");

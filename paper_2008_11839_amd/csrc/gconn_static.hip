@@ -1167,6 +1167,28 @@ gconn_status with_rule(int link, int find_rule, int splice, Fn&& fn) {
   switch (link) {
     case GCONN_LINK_ECL:
       return fn(Rule<kUnionAsync, kFindHalve, 0>{});
+    case GCONN_LINK_AFFOREST:
+      return fn(Rule<kUnionAfforest, kFindNaive, 0>{});
+    case GCONN_LINK_REM_LOCK:
+      if (splice == kSpliceAtomic) {
+        switch (find_rule) {
+          case kFindNaive: return fn(Rule<kUnionRemLock, kFindNaive, kSpliceAtomic>{});
+          case kFindSplit: return fn(Rule<kUnionRemLock, kFindSplit, kSpliceAtomic>{});
+          default: return fn(Rule<kUnionRemLock, kFindHalve, kSpliceAtomic>{});
+        }
+      }
+      if (splice == kSpliceSplitOne) {
+        switch (find_rule) {
+          case kFindNaive: return fn(Rule<kUnionRemLock, kFindNaive, kSpliceSplitOne>{});
+          case kFindSplit: return fn(Rule<kUnionRemLock, kFindSplit, kSpliceSplitOne>{});
+          default: return fn(Rule<kUnionRemLock, kFindHalve, kSpliceSplitOne>{});
+        }
+      }
+      switch (find_rule) {
+        case kFindNaive: return fn(Rule<kUnionRemLock, kFindNaive, kSpliceHalveOne>{});
+        case kFindSplit: return fn(Rule<kUnionRemLock, kFindSplit, kSpliceHalveOne>{});
+        default: return fn(Rule<kUnionRemLock, kFindHalve, kSpliceHalveOne>{});
+      }
     case GCONN_LINK_ASYNC:
       switch (find_rule) {
         case kFindNaive: return fn(Rule<kUnionAsync, kFindNaive, 0>{});
@@ -1240,7 +1262,7 @@ struct Run {
     wl.medium = reinterpret_cast<uint32_t*>(ws + L.medium);
     wl.segs = reinterpret_cast<uint2*>(ws + L.segs);
     wl.cap = L.sub_cap;
-    hooks = (o.link == GCONN_LINK_HOOKS) ? reinterpret_cast<uint32_t*>(ws + L.hooks) : nullptr;
+    hooks = needs_claims(o.link) ? reinterpret_cast<uint32_t*>(ws + L.hooks) : nullptr;
   }
 
   uint32_t gridN(uint64_t items) const { return grid_for(items, block); }
@@ -1752,7 +1774,7 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
     L.seg_cap = 2 * m / kSeg + 1;
     L.segs = take(8 * L.seg_cap);
   }
-  if (o.link == GCONN_LINK_HOOKS) L.hooks = take(4 * n);
+  if (needs_claims(o.link)) L.hooks = take(4 * n);
   if (csr && kout_prelink_applies(o)) L.resid = take(8 * n);
   const bool iterative =
       o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
@@ -1847,8 +1869,8 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
       GCONN_TRY(run.iterate(esrc, edst));
     }
     GCONN_TRY(prof_mark(kPhaseFinish, false, s));
-    if (finalize || o.link == GCONN_LINK_ECL) {
-      // ECL-CC's separate full-compress pass doubles as finalisation.
+    if (finalize || o.link == GCONN_LINK_ECL || o.link == GCONN_LINK_AFFOREST) {
+      // ECL-CC's and Afforest's separate full-compress pass doubles as finalisation.
       GCONN_TRY(prof_mark(kPhaseFinalize, true, s));
       const uint32_t grid = persistent_grid(k_finalize, block);
       k_finalize<<<grid, block, 0, s>>>(P, n, run.ctrl, run.wl, (sampled && csr) ? 1 : 0);

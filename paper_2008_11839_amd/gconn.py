@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libgconn.so")
 EMPTY = 0xFFFFFFFF
 
 SAMPLE = {"none": 0, "kout": 1, "hb": 2, "bfs": 3}
-LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt": 6, "lp": 7}
+LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt": 6, "lp": 7,
+        "afforest": 8, "rem_lock": 9}
 FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3}
 SPLICE = {"split_one": 0, "halve_one": 1, "splice_atomic": 2}
 SCHEDULE = {"auto": 0, "lane": 1, "step": 2}

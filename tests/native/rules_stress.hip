@@ -5,7 +5,8 @@
 //   rules_stress <edges.bin> <n> <rule> <threads> <labels.out> [atomic_compress]
 // edges.bin: uint32 pairs; rule: 0-3 Async (naive/split/halve/compress),
 // 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one),
-// 18-20 Rem-CAS with Rem's splice (naive/split/halve).
+// 18-20 Rem-CAS with Rem's splice (naive/split/halve), 21 G_Afforest's link,
+// 22-25 Rem-Lock (naive/split_one, split/split_one, halve/halve_one, split/splice).
 // Writes labels (root of every vertex, uint32) and prints the hook count.
 #include <hip/hip_runtime.h>
 
@@ -71,6 +72,11 @@ int main(int argc, char** argv) {
     case 18: c.atomic_compress = 1; run<Rule<kUnionRemCas, kFindNaive, kSpliceAtomic>>(e, c, threads); break;
     case 19: c.atomic_compress = 1; run<Rule<kUnionRemCas, kFindSplit, kSpliceAtomic>>(e, c, threads); break;
     case 20: c.atomic_compress = 1; run<Rule<kUnionRemCas, kFindHalve, kSpliceAtomic>>(e, c, threads); break;
+    case 21: run<Rule<kUnionAfforest, kFindNaive, 0>>(e, c, threads); break;
+    case 22: run<Rule<kUnionRemLock, kFindNaive, kSpliceSplitOne>>(e, c, threads); break;
+    case 23: run<Rule<kUnionRemLock, kFindSplit, kSpliceSplitOne>>(e, c, threads); break;
+    case 24: run<Rule<kUnionRemLock, kFindHalve, kSpliceHalveOne>>(e, c, threads); break;
+    case 25: run<Rule<kUnionRemLock, kFindSplit, kSpliceAtomic>>(e, c, threads); break;
     default: return 5;
   }
   std::vector<uint32_t> lab(n);

@@ -20,6 +20,8 @@ CONFIGS = [dict(sample=s, link=l, find=f, splice=sp)
                                ("kout", "rem_cas", "halve", "halve_one"),
                                ("kout", "rem_cas", "split", "splice_atomic"),
                                ("none", "rem_cas", "halve", "splice_atomic"),
+                               ("kout", "rem_lock", "split", "split_one"),
+                               ("none", "afforest", "naive", "split_one"),
                                ("kout", "async", "split", "split_one"),
                                ("kout", "early", "halve", "split_one"),
                                ("kout", "hooks", "split", "split_one"),

@@ -23,7 +23,9 @@ UF_RULES = ([("async", f, "split_one") for f in ("naive", "split", "halve", "com
             + [("early", f, "split_one") for f in ("naive", "split", "halve", "compress")]
             + [("rem_cas", f, s) for f in ("naive", "split", "halve")
                for s in ("split_one", "halve_one", "splice_atomic")]
-            + [("ecl", "halve", "split_one")])
+            + [("ecl", "halve", "split_one"), ("afforest", "naive", "split_one")]
+            + [("rem_lock", f, s) for f, s in (("naive", "split_one"), ("split", "split_one"),
+                                              ("halve", "halve_one"), ("split", "splice_atomic"))])
 SAMPLERS = ["none", "kout", "hb", "bfs"]
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
                "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]

@@ -16,7 +16,7 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "native", "rules_stress.hip")
 BIN = os.path.join(ROOT, "_build", "tests", "rules_stress")
-RULES = list(range(21))
+RULES = list(range(26))
 
 
 @pytest.fixture(scope="module")
