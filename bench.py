@@ -75,31 +75,109 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def serving_bench(G, src, dst, n, args) -> dict:
-    """Incremental serving: the graph's edge stream as insert batches of
-    log-uniform size in [1e4, 1e7] interleaved (coin flip) with query batches
-    of 1e5 uniform pairs, fed from host memory through gconn_server.  First
-    all requests at once (saturated throughput), then Poisson arrivals at 50%
-    and 80% of that rate; latency = submission -> answers on the host."""
-    import threading
-
+def update_stream(args):
+    """The incremental workload: an RMAT edge stream (both directions, so every
+    directed CSR entry is one update) cut into insert batches of log-uniform
+    size in [1e4, 1e7], each request an insert batch or a batch of 1e5 uniform
+    query pairs with probability 1/2, until the edges run out."""
     import numpy as np
 
     import graphgen
+    sc = args.serve_scale
+    n = 1 << sc
+    src, dst = graphgen.rmat_edges(sc, args.edge_factor * n, args.seed + 100)
+    graphgen.shuffle_edges(src, dst, args.seed + 100)
+    E = len(src)
     rng = np.random.default_rng(args.seed)
-    reqs, e = [], 0
-    while e < len(src):
+    reqs, e = [], 0  # inserts: (0, lo, hi); queries: (1, a, b)
+    while e < 2 * E:
         if rng.random() < 0.5:
             k = int(10 ** rng.uniform(4, 7))
-            reqs.append((0, src[e:e + k], dst[e:e + k]))
-            e += k
+            lo, hi = e, min(e + k, 2 * E)
+            if lo < E < hi:  # keep a batch inside one direction's pass
+                hi = E
+            reqs.append((0, lo, hi))
+            e = hi
         else:
             a, b = graphgen.uniform_pairs(n, 100_000, args.seed, len(reqs))
             reqs.append((1, a, b))
         if args.serve_requests and len(reqs) >= args.serve_requests:
             break
-    updates = sum(len(a) for k, a, _ in reqs if k == 0)
-    queries = sum(len(a) for k, a, _ in reqs if k == 1)
+    return n, src, dst, reqs
+
+
+def insert_slices(src, dst, lo, hi):
+    """Updates lo..hi of the two-pass stream: (src, dst) first, then (dst, src)."""
+    E = len(src)
+    if lo >= E:
+        return dst[lo - E:hi - E], src[lo - E:hi - E]
+    return src[lo:hi], dst[lo:hi]
+
+
+def incremental_bench(G, n, src, dst, reqs, args) -> dict:
+    """Device-resident replay of the update stream: all batches already in HBM,
+    one gconn_inc_* call per request on one stream, HIP events per batch."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    s_d = torch.from_numpy(src.view(np.int32)).to(dev)
+    d_d = torch.from_numpy(dst.view(np.int32)).to(dev)
+    qs = [(torch.from_numpy(a.view(np.int32)).to(dev), torch.from_numpy(b.view(np.int32)).to(dev))
+          for k, a, b in reqs if k == 1]
+    qout = torch.empty(100_000, dtype=torch.uint8, device=dev)
+    inc = G.Incremental(n, options=G.Options(sample="none", link="async", find="split"))
+    torch.cuda.synchronize()
+    evs, qi = [], 0
+    w0 = time.perf_counter()
+    for k, x, y in reqs:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if k == 0:
+            a, b = insert_slices(s_d, d_d, x, y)
+            inc.insert(a, b)
+        else:
+            inc.query(qs[qi][0], qs[qi][1], out=qout)
+            qi += 1
+        e1.record()
+        evs.append((k, e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    lat_i = [a.elapsed_time(b) for k, a, b in evs if k == 0]
+    lat_q = [a.elapsed_time(b) for k, a, b in evs if k == 1]
+    updates = sum(y - x for k, x, y in reqs if k == 0)
+    # invariants of the final labels: every streamed edge inside one label,
+    # labels are minima (L[v] <= v) and fixed points (L[L[v]] == L[v])
+    lab = inc.labels().long()
+    last = max((y for k, x, y in reqs if k == 0), default=0)
+    m_in = min(last, len(src))
+    ok = True
+    for c0 in range(0, m_in, 1 << 27):
+        c1 = min(m_in, c0 + (1 << 27))
+        ok = ok and bool((lab[s_d[c0:c1].long()] == lab[d_d[c0:c1].long()]).all().item())
+    ok = ok and bool((lab <= torch.arange(n, device=dev)).all().item())
+    ok = ok and bool((lab[lab] == lab).all().item())
+    del lab
+    inc.close()
+    del s_d, d_d, qs
+    return {"updates": updates, "insert_batches": len(lat_i), "query_batches": len(lat_q),
+            "insert_updates_per_s": round(updates / (sum(lat_i) * 1e-3), 1),
+            "stream_updates_per_s": round(updates / wall, 1),
+            "insert_batch_ms_p50": round(percentile(lat_i, 50), 4),
+            "insert_batch_ms_p99": round(percentile(lat_i, 99), 4),
+            "query_batch_ms_p50": round(percentile(lat_q, 50), 4),
+            "query_batch_ms_p99": round(percentile(lat_q, 99), 4),
+            "label_invariants_hold": ok}
+
+
+def serving_bench(G, n, src, dst, reqs, args) -> dict:
+    """Host-fed serving of the update stream through gconn_server: all requests
+    at once (saturated throughput), then Poisson arrivals at 50 %, 80 % and
+    95 % of that rate; latency = submission -> applied / answers on the host."""
+    import numpy as np
+    rng = np.random.default_rng(args.seed)
+    host = [(0,) + insert_slices(src, dst, x, y) if k == 0 else (1, x, y) for k, x, y in reqs]
+    updates = sum(len(a) for k, a, _ in host if k == 0)
+    queries = sum(len(a) for k, a, _ in host if k == 1)
     opts = G.Options(sample="none", link="async", find="split")
 
     def run(rate):
@@ -107,11 +185,11 @@ def serving_bench(G, src, dst, n, args) -> dict:
         tickets = []
         t0 = time.perf_counter()
         if rate is None:
-            tickets = [srv.submit(k, a, b) for k, a, b in reqs]
+            tickets = [srv.submit(k, a, b) for k, a, b in host]
         else:
-            gaps = rng.exponential(1.0 / rate, size=len(reqs))
+            gaps = rng.exponential(1.0 / rate, size=len(host))
             nxt = time.perf_counter()
-            for (k, a, b), g in zip(reqs, gaps):
+            for (k, a, b), g in zip(host, gaps):
                 nxt += g
                 while time.perf_counter() < nxt:
                     pass
@@ -123,20 +201,17 @@ def serving_bench(G, src, dst, n, args) -> dict:
         return wall, lat, recs
 
     wall, lat, recs = run(None)
-    sat_rate = len(reqs) / wall
-    out = {"workload": f"RMAT-{args.scale} edge stream ({updates} updates in {sum(1 for r in reqs if r[0] == 0)} "
-                       f"insert batches, log-uniform 1e4..1e7) + {sum(1 for r in reqs if r[0] == 1)} "
-                       "query batches of 1e5 pairs, host-fed, 4 streams, 512 MB arena",
-           "saturated": {"updates_per_s": round(updates / wall, 1),
+    sat_rate = len(host) / wall
+    out = {"saturated": {"updates_per_s": round(updates / wall, 1),
                          "requests_per_s": round(sat_rate, 2), "wall_s": round(wall, 3),
                          "latency_ms_p50": round(percentile(lat, 50), 3),
                          "latency_ms_p99": round(percentile(lat, 99), 3)}}
-    for rho in (0.5, 0.8):
+    for rho in (0.5, 0.8, 0.95):
         wall, lat, recs = run(rho * sat_rate)
         out[f"load_{rho}"] = {"updates_per_s": round(updates / wall, 1),
                               "latency_ms_p50": round(percentile(lat, 50), 3),
                               "latency_ms_p99": round(percentile(lat, 99), 3)}
-    out["queries"] = queries
+    out["updates"], out["queries"] = updates, queries
     return out
 
 
@@ -270,7 +345,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the spanning-forest and incremental measurements")
-    ap.add_argument("--inc-batch", type=int, default=1_000_000)
+    ap.add_argument("--serve-scale", type=int, default=26,
+                    help="RMAT scale of the incremental update stream (26 = the workload)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -452,64 +528,27 @@ def main() -> int:
         log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")
         del fu, fv, ws_f
 
-        # -------------------------------------------------------- incremental batches
-        # the generated edge list holds each undirected edge once, in random order
-        s_in = torch.from_numpy(src.view(np.int32)).to(dev)
-        d_in = torch.from_numpy(dst.view(np.int32)).to(dev)
-        qa, qb = graphgen.uniform_pairs(n, 100_000, args.seed, 0)
-        qa_t = torch.from_numpy(qa.view(np.int32)).to(dev)
-        qb_t = torch.from_numpy(qb.view(np.int32)).to(dev)
-        qout = torch.empty(len(qa), dtype=torch.uint8, device=dev)
-        k_total = s_in.numel()
-        B = args.inc_batch
-        inc_opts = G.Options(sample="none", link="async", find="split")
-        inc = G.Incremental(n, options=inc_opts)
-        torch.cuda.synchronize()
-        lat_ins, lat_q = [], []
-        evs = []
-        w0 = time.perf_counter()
-        for b0 in range(0, k_total, B):
-            e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e_a.record(stream)
-            inc.insert(s_in[b0:b0 + B], d_in[b0:b0 + B])
-            e_b.record(stream)
-            q_a, q_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            q_a.record(stream)
-            inc.query(qa_t, qb_t, out=qout)
-            q_b.record(stream)
-            evs.append((e_a, e_b, q_a, q_b))
-        torch.cuda.synchronize()
-        inc_wall = time.perf_counter() - w0
-        for e_a, e_b, q_a, q_b in evs:
-            lat_ins.append(e_a.elapsed_time(e_b))
-            lat_q.append(q_a.elapsed_time(q_b))
-        ins_ms = sum(lat_ins)
-        inc_labels = G.to_u32(inc.labels())
-        inc.close()
-        result["incremental"] = {
-            "workload": f"{C.name} undirected edges streamed once in generation order, "
-                        f"insert batches of {B} interleaved with 1e5-pair query batches, "
-                        "device-resident, Union-Async + FindSplit",
-            "updates": k_total, "insert_updates_per_s": round(k_total / (ins_ms * 1e-3), 1),
-            "insert_batch_ms_p50": round(percentile(lat_ins, 50), 4),
-            "insert_batch_ms_p99": round(percentile(lat_ins, 99), 4),
-            "query_batch_ms_p50": round(percentile(lat_q, 50), 4),
-            "query_batch_ms_p99": round(percentile(lat_q, 99), 4),
-            "wall_updates_per_s": round(k_total / inc_wall, 1),
-            "labels_match_static": bool(np.array_equal(inc_labels, got)),
-        }
-        log(f"incremental {result['incremental']}")
-        del s_in, d_in
-
     # ------------------------------------------------------------ mixed insert/query batches
     if not args.no_extras and not args.no_mixed:
         result["incremental_mixed"] = mixed_bench(G, args)
         log(f"incremental_mixed {result['incremental_mixed']}")
 
-    # ------------------------------------------------------------ serving loop (host-fed)
-    if not args.no_extras and not args.no_serving:
-        result["serving"] = serving_bench(G, src, dst, n, args)
-        log(f"serving {result['serving']}")
+    # ------------------------------------------------------------ incremental stream
+    if not args.no_extras:
+        t0 = time.time()
+        sn, ssrc, sdst, reqs = update_stream(args)
+        n_ins = sum(1 for r in reqs if r[0] == 0)
+        result["incremental"] = {
+            "workload": f"RMAT-{args.serve_scale} ef{args.edge_factor} edge stream, both directions "
+                        f"({sum(y - x for k, x, y in reqs if k == 0)} updates in {n_ins} insert "
+                        f"batches, log-uniform 1e4..1e7) with {len(reqs) - n_ins} query batches "
+                        "of 1e5 uniform pairs interleaved by coin flip; Union-Async + FindSplit",
+            "device_resident": incremental_bench(G, sn, ssrc, sdst, reqs, args)}
+        log(f"incremental stream built in {time.time() - t0:.1f}s: {result['incremental']}")
+        if not args.no_serving:
+            result["incremental"]["host_fed_server"] = serving_bench(G, sn, ssrc, sdst, reqs, args)
+            log(f"serving {result['incremental']['host_fed_server']}")
+        del ssrc, sdst, reqs
 
     # ------------------------------------------------------------ many-graph batch
     if not args.no_extras and not args.no_batched:

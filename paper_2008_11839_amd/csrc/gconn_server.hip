@@ -36,6 +36,29 @@ namespace gconn {
 namespace {
 
 constexpr uint64_t kGranule = 256;
+constexpr uint64_t kInsertChunk = 4u << 20;  // edges per chunk of a large insert batch
+
+// Host copy into pinned staging, split over a few threads for large requests:
+// one thread's memcpy (~10 GB/s) would otherwise cap the host-fed rate well
+// below what the host-to-device link carries.
+void staged_copy(void* dst, const void* src, size_t bytes) {
+  constexpr size_t kChunk = 2u << 20;
+  const size_t parts = std::min<size_t>(8, bytes / kChunk);
+  if (parts < 2) {
+    std::memcpy(dst, src, bytes);
+    return;
+  }
+  std::vector<std::thread> ts;
+  const size_t per = (bytes + parts - 1) / parts;
+  for (size_t i = 1; i < parts; ++i) {
+    const size_t lo = i * per, len = std::min(bytes, lo + per) - lo;
+    ts.emplace_back([=] {
+      std::memcpy(static_cast<char*>(dst) + lo, static_cast<const char*>(src) + lo, len);
+    });
+  }
+  std::memcpy(dst, src, std::min(per, bytes));
+  for (auto& t : ts) t.join();
+}
 
 // First-fit allocator over [0, size) with coalescing of free ranges.
 class RangeAlloc {
@@ -159,13 +182,24 @@ struct gconn_server {
     uint8_t* host = staging + r.at;
     uint32_t* da = reinterpret_cast<uint32_t*>(dev);
     uint32_t* db = da + r.count;
-    std::memcpy(host, r.a, 4 * r.count);
-    std::memcpy(host + 4 * r.count, r.b, 4 * r.count);
-    GCONN_HIP(hipMemcpyAsync(dev, host, 8 * r.count, hipMemcpyHostToDevice, s));
     if (r.kind == GCONN_REQ_INSERT) {
-      uint32_t* H = nullptr;  // Union-Hooks is not offered by the server
-      GCONN_TRY(launch_insert(cfg.options, P, H, da, db, r.count, s));
+      // Large insert batches go in chunks, so that the host copy of one chunk
+      // overlaps the transfer and the union kernel of the previous one.
+      uint32_t* H = nullptr;  // rules with a claim array are not offered by the server
+      uint32_t* ha = reinterpret_cast<uint32_t*>(host);
+      uint32_t* hb = ha + r.count;
+      for (uint64_t lo = 0; lo < r.count; lo += kInsertChunk) {
+        const uint64_t len = std::min<uint64_t>(kInsertChunk, r.count - lo);
+        staged_copy(ha + lo, r.a + lo, 4 * len);
+        staged_copy(hb + lo, r.b + lo, 4 * len);
+        GCONN_HIP(hipMemcpyAsync(da + lo, ha + lo, 4 * len, hipMemcpyHostToDevice, s));
+        GCONN_HIP(hipMemcpyAsync(db + lo, hb + lo, 4 * len, hipMemcpyHostToDevice, s));
+        GCONN_TRY(launch_insert(cfg.options, P, H, da + lo, db + lo, len, s));
+      }
     } else {
+      staged_copy(host, r.a, 4 * r.count);
+      staged_copy(host + 4 * r.count, r.b, 4 * r.count);
+      GCONN_HIP(hipMemcpyAsync(dev, host, 8 * r.count, hipMemcpyHostToDevice, s));
       uint8_t* dout = dev + 8 * r.count;
       GCONN_TRY(launch_query(cfg.options, P, da, db, r.count, dout, s));
       GCONN_HIP(hipMemcpyAsync(host + 8 * r.count, dout, r.count, hipMemcpyDeviceToHost, s));
