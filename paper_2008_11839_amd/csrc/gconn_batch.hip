@@ -69,8 +69,19 @@ __global__ void k_batch_sample(const uint64_t* __restrict__ off, const uint32_t*
                                const uint8_t* __restrict__ graph_class, BatchClasses cl, LinkCtx lc,
                                Ctrl* stats) {
   unsigned long long sampled = 0;
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    const BatchClass& bc = class_of(cl, graph_class, tile_graph[base >> 6]);
+  // Tiles are visited in a scrambled order (odd multiplier modulo the next
+  // power of two, out-of-range values skipped): the tiles of one small graph
+  // would otherwise all run at the same moment, and its few smallest ids --
+  // every vertex's first sampled neighbours -- would take all their CASes at
+  // once.  Scrambled, a graph's unions spread over the whole launch.
+  const uint64_t tiles = ((uint64_t)n + 63) >> 6;
+  uint64_t span = 1;
+  while (span < tiles) span <<= 1;
+  for (uint64_t t = wave_index(); t < span; t += wave_count()) {
+    const uint64_t tile = (t * 0x9E3779B97F4A7C15ull) & (span - 1);
+    if (tile >= tiles) continue;  // uniform over the wave
+    const uint64_t base = tile << 6;
+    const BatchClass& bc = class_of(cl, graph_class, tile_graph[tile]);
     if (!bc.sample) continue;  // uniform over the wave: one graph per tile
     const uint64_t v = base + lane();
     const uint64_t b = off[v], deg = off[v + 1] - b;
