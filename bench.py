@@ -280,6 +280,57 @@ def batched_bench(G, args) -> dict:
             "labels_identical": bool(same)}
 
 
+def other_configs_bench(G, args) -> dict:
+    """The other static workloads: ER (n = 1e5, 1e6 draws: a latency / launch
+    overhead case) and the bond-percolation grids (2D 4096^2 at p = 0.7, 3D
+    256^3 at p = 0.6: many components, long chains), each over union-find with
+    and without sampling and the round-based finishes (SV, Liu-Tarjan PRF,
+    label propagation), labels checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import oracle
+    dev = torch.device("cuda", 0)
+    work = {"er_1e5": lambda: graphgen.er(100_000, 1_000_000, args.seed),
+            "grid2d_4096_p0.7": lambda: graphgen.grid2d(4096, 4096, 0.7, args.seed),
+            "grid3d_256_p0.6": lambda: graphgen.grid3d(256, 256, 256, 0.6, args.seed)}
+    cfgs = [dict(sample="kout", link="rem_cas", find="split"),
+            dict(sample="none", link="rem_cas", find="split"),
+            dict(sample="none", link="async", find="halve"),
+            dict(sample="kout", link="sv"), dict(sample="kout", link="lt", lt_variant="PRF"),
+            dict(sample="kout", link="lp"), dict(sample="none", link="sv"),
+            dict(sample="none", link="lp")]
+    out = {}
+    for name, make in work.items():
+        C = make()
+        want = oracle.cc(C.n, C.offsets, C.nbrs)
+        comps = int((want == np.arange(C.n, dtype=np.uint32)).sum())
+        dg = G.csr(C.offsets, C.nbrs, C.n)
+        lab = torch.empty(C.n, dtype=torch.int32, device=dev)
+        res = {"n": C.n, "m_directed": C.m, "components": comps, "runs": []}
+        for cfg in cfgs:
+            o = G.Options(**cfg)
+            ws = G.alloc_workspace(G.workspace_size(dg, o))
+            _, st = G.cc(dg, labels=lab, options=o, workspace=ws, stats=True)
+            ok = bool(np.array_equal(G.to_u32(lab), want))
+            reps = 5
+            G.cc(dg, labels=lab, options=o, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                G.cc(dg, labels=lab, options=o, workspace=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            res["runs"].append({**cfg, "ms": round(ms, 4),
+                                "gedges_per_s": round(C.m / (ms * 1e-3) / 1e9, 2),
+                                "rounds": st["rounds"], "labels_match_oracle": ok})
+            del ws
+        out[name] = res
+        del dg, lab
+    return out
+
+
 def mixed_bench(G, args) -> dict:
     """Mixed insert/query batches over a Barabasi-Albert edge stream, for several
     insert-to-query ratios (the paper's mixed-batch experiment): device-resident
@@ -352,6 +403,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the ER and grid workloads")
     ap.add_argument("--mixed-scale", type=int, default=22,
                     help="Barabasi-Albert stream of 2^scale vertices, 10 edges each")
     ap.add_argument("--batch-graphs", type=int, default=2000)
@@ -529,6 +581,11 @@ def main() -> int:
                                      "forest_edges": filled, "n_minus_c": n - comps}
         log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")
         del fu, fv, ws_f
+
+    # ------------------------------------------------------------ ER and grid workloads
+    if not args.no_extras and not args.no_configs:
+        result["other_configs"] = other_configs_bench(G, args)
+        log(f"other configs {result['other_configs']}")
 
     # ------------------------------------------------------------ mixed insert/query batches
     if not args.no_extras and not args.no_mixed:
