@@ -1267,6 +1267,18 @@ struct Run {
 
   uint32_t gridN(uint64_t items) const { return grid_for(items, block); }
 
+  // Sampling grid: one lane per 6 vertices up to 2^18 vertices, one per 16
+  // beyond, never above `full`.  With every vertex of a small graph in flight
+  // at once, the unions of all the vertices whose first sampled neighbours are
+  // the same few small ids hit those roots together and serialise (measured:
+  // ER with 1e5 vertices 3x, with 1e6 vertices 3.6x slower at a full grid);
+  // graphs of millions of vertices keep the full grid.
+  uint32_t contention_grid(uint32_t full, uint64_t n) const {
+    const uint64_t per_lane = n <= (1ull << 18) ? 6 : 16;
+    const uint64_t want = (n + per_lane * block - 1) / (per_lane * block);
+    return (uint32_t)std::max<uint64_t>(16, std::min<uint64_t>(full, want));
+  }
+
   // Liu-Tarjan variants whose connect rule sends labels to the edge endpoints
   // under Update (CUSA, CUFA, EUSA, EUS, EUFA, EUF) may re-point a vertex of
   // the L_max group away from its group, whose internal edges the finish never
@@ -1322,7 +1334,7 @@ struct Run {
         GCONN_LAUNCHED("k_kout_prelink");
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
           using R = decltype(rule);
-          k_kout_residual<R><<<gridN(n), block, 0, s>>>(res, n, link_ctx());
+          k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n, link_ctx());
           GCONN_LAUNCHED("k_kout_residual");
           return GCONN_OK;
         }));
@@ -1347,7 +1359,7 @@ struct Run {
       } else {
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
           using R = decltype(rule);
-          const uint32_t grid = persistent_grid(k_sample_kout_pf<R, OffT>, block);
+          const uint32_t grid = contention_grid(persistent_grid(k_sample_kout_pf<R, OffT>, block), n);
           k_sample_kout_pf<R, OffT><<<grid, block, 0, s>>>(off, g.nbrs, n, o.k, o.kout_random,
                                                            o.seed ^ 0x6b6f7574ull, link_ctx(), st);
           GCONN_LAUNCHED("k_sample_kout_pf");
