@@ -266,6 +266,15 @@ def batched_bench(G, args) -> dict:
             G.cc(d, labels=l, options=opt1, workspace=ws_1)
     torch.cuda.synchronize()
     t_loop = (time.perf_counter() - t0) / reps
+    ex = B.capture_batch(db, classes, lab_b, workspace=ws_b)
+    ex.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ex.launch()
+    torch.cuda.synchronize()
+    t_cap = (time.perf_counter() - t0) / reps
+    ex.close()
     lb = lab_b.cpu().numpy().view(np.uint32)
     same = all(np.array_equal(lb[int(hb.vbase[i]):int(hb.vbase[i]) + g.n], G.to_u32(l))
                for i, (g, l) in enumerate(zip(graphs, labs)))
@@ -273,7 +282,8 @@ def batched_bench(G, args) -> dict:
                         "ER or RMAT by coin flip, edge factor 8..32",
             "graphs": len(graphs), "n": total_n, "m_directed": total_m,
             "classes": {k: tuner.table[k]["choice"] for k in sorted(set(keys))},
-            "batched_ms": round(t_batch * 1e3, 3), "per_graph_launches_ms": round(t_loop * 1e3, 3),
+            "batched_ms": round(t_batch * 1e3, 3), "batched_captured_ms": round(t_cap * 1e3, 3),
+            "per_graph_launches_ms": round(t_loop * 1e3, 3),
             "speedup": round(t_loop / t_batch, 2),
             "batched_gedges_per_s": round(total_m / t_batch / 1e9, 2),
             "per_graph_gedges_per_s": round(total_m / t_loop / 1e9, 2),
@@ -322,9 +332,21 @@ def other_configs_bench(G, args) -> dict:
                 G.cc(dg, labels=lab, options=o, workspace=ws)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / reps
-            res["runs"].append({**cfg, "ms": round(ms, 4),
-                                "gedges_per_s": round(C.m / (ms * 1e-3) / 1e9, 2),
-                                "rounds": st["rounds"], "labels_match_oracle": ok})
+            run = {**cfg, "ms": round(ms, 4), "gedges_per_s": round(C.m / (ms * 1e-3) / 1e9, 2),
+                   "rounds": st["rounds"], "labels_match_oracle": ok}
+            if cfg["link"] not in ("sv", "lt", "lp"):
+                # the same pipeline captured once into a HIP graph, replayed
+                ex = G.capture_cc(dg, lab, options=o, workspace=ws)
+                ex.launch()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    ex.launch()
+                torch.cuda.synchronize()
+                run["captured_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
+                run["captured_labels_match_oracle"] = bool(np.array_equal(G.to_u32(lab), want))
+                ex.close()
+            res["runs"].append(run)
             del ws
         out[name] = res
         del dg, lab

@@ -287,6 +287,29 @@ gconn_status gconn_autotune(const gconn_graph* graphs, uint32_t num_graphs,
                             size_t workspace_bytes, void* stream, uint32_t* best,
                             double* times_ms);
 
+/* Captured pipelines (HIP graphs).  gconn_cc_capture / gconn_cc_batch_capture
+ * validate their arguments exactly as gconn_cc / gconn_cc_batch do, then
+ * record the whole launch sequence of one run into a HIP graph (on a private
+ * stream; nothing runs yet) and instantiate it.  gconn_exec_launch replays it
+ * on `stream` with one launch: the same pointers, sizes and options, reading
+ * whatever the input buffers hold at that time, writing labels_out again.
+ * Launch-bound callers (small graphs, many repeats) save the per-kernel launch
+ * cost.  Only pipelines with no host round trip can be captured: union-find
+ * finishes (no SV, LT or LP) with k-out, hook-based or no sampling (BFS checks
+ * its frontier on the host), options.validate = 0, no statistics, and phase
+ * profiling off -- anything else is GCONN_EUNSUPPORTED.  The caller keeps
+ * every buffer alive while the handle exists; replays on one handle must not
+ * overlap (they share the workspace).  Host-owned handle. */
+typedef struct gconn_exec gconn_exec;
+gconn_status gconn_cc_capture(const gconn_graph* g, uint32_t* labels_out, void* workspace,
+                              size_t workspace_bytes, const gconn_options* opt, gconn_exec** out);
+gconn_status gconn_cc_batch_capture(const gconn_batch* b, uint32_t* labels_out, void* workspace,
+                                    size_t workspace_bytes, const gconn_class_options* classes,
+                                    uint32_t num_classes, uint32_t lmax_samples, uint64_t seed,
+                                    gconn_exec** out);
+gconn_status gconn_exec_launch(gconn_exec* e, void* stream);
+gconn_status gconn_exec_destroy(gconn_exec* e);
+
 /* ------------------------------------------------------------- serving
  * A request loop over one resident parent array (incremental connectivity
  * served online).  Clients submit insert or query batches from host memory

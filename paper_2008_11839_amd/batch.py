@@ -134,6 +134,23 @@ def cc_batch(db: DeviceBatch, classes: list, labels: torch.Tensor | None = None,
     return (labels, G._stats_dict(st)) if stats else labels
 
 
+def capture_batch(db: DeviceBatch, classes: list, labels: torch.Tensor,
+                  workspace: torch.Tensor | None = None, lmax_samples: int = 1024,
+                  seed: int = 1) -> "G.Exec":
+    """Record one gconn_cc_batch run into a HIP graph; Exec.launch() replays it."""
+    lib = G.lib()
+    if workspace is None:
+        b = ctypes.c_size_t()
+        G._check(lib.gconn_cc_batch_workspace_size(ctypes.byref(db.c), ctypes.byref(b)))
+        workspace = G.alloc_workspace(b.value, db.offsets.device)
+    arr = (G._ClassOptions * len(classes))(*[class_options(c) for c in classes])
+    h = ctypes.c_void_p()
+    G._check(lib.gconn_cc_batch_capture(ctypes.byref(db.c), labels.data_ptr() if db.host.n else None,
+                                        workspace.data_ptr(), workspace.numel(), arr, len(classes),
+                                        lmax_samples, seed, ctypes.byref(h)))
+    return G.Exec(h, (db, labels, workspace, arr))
+
+
 def autotune(device_graphs: list, candidates=CANDIDATES, reps: int = 3, stream=None):
     """Index of the fastest candidate over the given graphs, and the totals (ms)."""
     lib = G.lib()

@@ -147,6 +147,55 @@ struct gconn_inc {
   gconn_options opt;
 };
 
+struct gconn_exec {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Record body(stream) on a private non-blocking stream into a HIP graph and
+// instantiate it.  Argument checks happen before; nothing runs on the device.
+template <class Body>
+gconn_status capture_exec(Body&& body, gconn_exec** out) {
+  if (gconn::profiling())
+    return gconn::fail(GCONN_EUNSUPPORTED, "phase profiling is on: its events cannot be captured");
+  hipStream_t cs = nullptr;
+  GCONN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return gconn::hip_fail(e, "hipStreamBeginCapture");
+  }
+  const gconn_status st = body(cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != GCONN_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return gconn::hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return gconn::hip_fail(e, "hipGraphInstantiate");
+  }
+  gconn_exec* h = new (std::nothrow) gconn_exec;
+  if (!h) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return gconn::fail(GCONN_EINVAL, "host allocation of the handle failed");
+  }
+  h->graph = graph;
+  h->exec = exec;
+  *out = h;
+  return GCONN_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void gconn_options_default(gconn_options* o) {
@@ -369,6 +418,66 @@ gconn_status gconn_autotune(const gconn_graph* graphs, uint32_t num_graphs,
   clear_error();
   return autotune(graphs, num_graphs, candidates, num_candidates, reps, labels_scratch, workspace,
                   workspace_bytes, static_cast<hipStream_t>(stream), best, times_ms);
+}
+
+gconn_status gconn_cc_capture(const gconn_graph* g, uint32_t* labels_out, void* workspace,
+                              size_t workspace_bytes, const gconn_options* opt, gconn_exec** out) {
+  clear_error();
+  if (!out) return fail(GCONN_EINVAL, "out is NULL");
+  *out = nullptr;
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  if (!is_union_find(o.link))
+    return fail(GCONN_EUNSUPPORTED, "SV, LT and LP check their rounds on the host: not capturable");
+  if (o.sample == GCONN_SAMPLE_BFS)
+    return fail(GCONN_EUNSUPPORTED, "BFS sampling checks its frontier on the host: not capturable");
+  if (o.validate) return fail(GCONN_EUNSUPPORTED, "validation synchronises: not capturable");
+  GCONN_TRY(check_device_ready());
+  GCONN_TRY(check_graph(g));
+  if (g->format == GCONN_COO) o.sample = GCONN_SAMPLE_NONE;
+  if (g->n > 0) GCONN_TRY(check_device_ptr(labels_out, "labels_out"));
+  const WsLayout L = plan_workspace(*g, o, false, true);
+  GCONN_TRY(check_workspace(workspace, workspace_bytes, L.total));
+  const gconn_graph gc = *g;
+  return capture_exec(
+      [&](hipStream_t cs) {
+        return run_static(gc, labels_out, nullptr, nullptr, true, static_cast<uint8_t*>(workspace),
+                          L, o, nullptr, cs);
+      },
+      out);
+}
+
+gconn_status gconn_cc_batch_capture(const gconn_batch* b, uint32_t* labels_out, void* workspace,
+                                    size_t workspace_bytes, const gconn_class_options* classes,
+                                    uint32_t num_classes, uint32_t lmax_samples, uint64_t seed,
+                                    gconn_exec** out) {
+  clear_error();
+  if (!out) return fail(GCONN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!b) return fail(GCONN_EINVAL, "batch is NULL");
+  const gconn_batch bc = *b;
+  return capture_exec(
+      [&](hipStream_t cs) {
+        return run_batch(&bc, labels_out, workspace, workspace_bytes, classes, num_classes,
+                         lmax_samples, seed, nullptr, cs);
+      },
+      out);
+}
+
+gconn_status gconn_exec_launch(gconn_exec* e, void* stream) {
+  clear_error();
+  if (!e) return fail(GCONN_EINVAL, "handle is NULL");
+  GCONN_HIP(hipGraphLaunch(e->exec, static_cast<hipStream_t>(stream)));
+  return GCONN_OK;
+}
+
+gconn_status gconn_exec_destroy(gconn_exec* e) {
+  clear_error();
+  if (!e) return GCONN_OK;
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  delete e;
+  return GCONN_OK;
 }
 
 gconn_status gconn_profile_enable(int on) { return profile_enable(on); }

@@ -94,6 +94,7 @@ EXPORTS = ["gconn_server_create", "gconn_server_submit", "gconn_server_wait",
            "gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
            "gconn_inc_query_batch", "gconn_inc_mixed_batch", "gconn_inc_labels", "gconn_inc_destroy",
+           "gconn_cc_capture", "gconn_cc_batch_capture", "gconn_exec_launch", "gconn_exec_destroy",
            "gconn_status_string", "gconn_last_error", "gconn_version"]
 
 _lib = None
@@ -128,6 +129,12 @@ def lib() -> ctypes.CDLL:
         L.gconn_inc_query_batch.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp]
         L.gconn_inc_mixed_batch.restype = ctypes.c_int
         L.gconn_inc_mixed_batch.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, vp, vp]
+        L.gconn_cc_capture.restype = ctypes.c_int
+        L.gconn_cc_capture.argtypes = [gp, vp, vp, sz, op, ctypes.POINTER(vp)]
+        L.gconn_exec_launch.restype = ctypes.c_int
+        L.gconn_exec_launch.argtypes = [vp, vp]
+        L.gconn_exec_destroy.restype = ctypes.c_int
+        L.gconn_exec_destroy.argtypes = [vp]
         L.gconn_inc_labels.restype = ctypes.c_int
         L.gconn_inc_labels.argtypes = [vp, vp, vp]
         L.gconn_inc_destroy.restype = ctypes.c_int
@@ -138,6 +145,9 @@ def lib() -> ctypes.CDLL:
         L.gconn_cc_batch.restype = ctypes.c_int
         L.gconn_cc_batch.argtypes = [bp, vp, vp, sz, cp, ctypes.c_uint32, ctypes.c_uint32,
                                      ctypes.c_uint64, stp, vp]
+        L.gconn_cc_batch_capture.restype = ctypes.c_int
+        L.gconn_cc_batch_capture.argtypes = [bp, vp, vp, sz, cp, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_uint64, ctypes.POINTER(vp)]
         L.gconn_autotune.restype = ctypes.c_int
         L.gconn_autotune.argtypes = [gp, ctypes.c_uint32, op, ctypes.c_uint32, ctypes.c_uint32, vp,
                                      vp, sz, vp, ctypes.POINTER(ctypes.c_uint32),
@@ -308,6 +318,43 @@ def cc(g: DeviceGraph, labels: torch.Tensor | None = None, options: Options | No
                           workspace.numel(), ctypes.byref(o), ctypes.byref(st) if st else None,
                           _stream(stream)))
     return (labels, _stats_dict(st)) if stats else labels
+
+
+class Exec:
+    """A captured pipeline (gconn_cc_capture / gconn_cc_batch_capture): launch()
+    replays it on a stream.  Holds references to every buffer it reads or
+    writes, so they outlive the handle."""
+
+    def __init__(self, handle: ctypes.c_void_p, keep: tuple):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self, stream=None) -> None:
+        _check(lib().gconn_exec_launch(self._h, _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().gconn_exec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture_cc(g: DeviceGraph, labels: torch.Tensor, options: Options | None = None,
+               workspace: torch.Tensor | None = None) -> Exec:
+    """Record one gconn_cc run into a HIP graph; Exec.launch() replays it."""
+    o = (options or Options()).to_c()
+    if workspace is None:
+        workspace = alloc_workspace(workspace_size(g, options))
+    h = ctypes.c_void_p()
+    _check(lib().gconn_cc_capture(ctypes.byref(g.c), _ptr(labels) if g.n else None,
+                                  workspace.data_ptr(), workspace.numel(), ctypes.byref(o),
+                                  ctypes.byref(h)))
+    return Exec(h, (g, labels, workspace))
 
 
 def spanning_forest(g: DeviceGraph, want_labels: bool = True, options: Options | None = None,
