@@ -236,7 +236,7 @@ def batched_bench(G, args) -> dict:
     keys = tuner.tune(graphs)
     classes, gclass = tuner.classes_for(keys)
     hb = B.concat(graphs)
-    db = B.upload(hb, graph_class=gclass)
+    db = B.upload(hb, graph_class=gclass, block=tuner.batch_block(keys, graphs))
     ws_b = torch.empty(0)
     import ctypes
     bb = ctypes.c_size_t()
@@ -282,6 +282,7 @@ def batched_bench(G, args) -> dict:
                         "ER or RMAT by coin flip, edge factor 8..32",
             "graphs": len(graphs), "n": total_n, "m_directed": total_m,
             "classes": {k: tuner.table[k]["choice"] for k in sorted(set(keys))},
+            "batch_block": int(db.c.block),
             "batched_ms": round(t_batch * 1e3, 3), "batched_captured_ms": round(t_cap * 1e3, 3),
             "per_graph_launches_ms": round(t_loop * 1e3, 3),
             "speedup": round(t_loop / t_batch, 2),

@@ -252,6 +252,9 @@ typedef struct gconn_batch {
   const uint32_t* nbrs;        /* device, m global neighbour ids                   */
   const uint32_t* vbase;       /* device, G + 1: vbase[0] = 0, multiples of 64     */
   const uint8_t* graph_class;  /* device, G class indices (NULL: every graph in 0) */
+  uint32_t block;              /* threads per workgroup of every batch kernel:
+                                  0 = 256, else a multiple of 64 in [64, 1024]     */
+  uint32_t reserved;
 } gconn_batch;
 
 typedef struct gconn_class_options {

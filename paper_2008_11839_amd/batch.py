@@ -20,6 +20,8 @@ import torch
 from . import gconn as G
 
 # Candidate option sets per class (the batched kernels support these rules).
+BLOCKS = (128, 256, 512, 1024)  # workgroup shapes tried for each class's chosen rule
+
 CANDIDATES = [
     dict(sample="kout", link="rem_cas", find="split", splice="split_one"),
     dict(sample="kout", link="rem_cas", find="naive", splice="split_one"),
@@ -90,7 +92,7 @@ class DeviceBatch:
     c: G._Batch
 
 
-def upload(hb: HostBatch, graph_class=None, device="cuda") -> DeviceBatch:
+def upload(hb: HostBatch, graph_class=None, device="cuda", block: int = 0) -> DeviceBatch:
     off = torch.from_numpy(hb.offsets.view(np.int64)).to(device)
     nb = torch.from_numpy(hb.nbrs.view(np.int32)).to(device)
     vb = torch.from_numpy(hb.vbase.view(np.int32)).to(device)
@@ -101,6 +103,7 @@ def upload(hb: HostBatch, graph_class=None, device="cuda") -> DeviceBatch:
     c.num_graphs, c.n, c.m = hb.num_graphs, hb.n, hb.m
     c.offsets, c.nbrs, c.vbase = off.data_ptr(), (nb.data_ptr() if hb.m else None), vb.data_ptr()
     c.graph_class = gc.data_ptr() if gc is not None else None
+    c.block = block
     return DeviceBatch(hb, off, nb, vb, gc, c)
 
 
@@ -197,11 +200,24 @@ class Autotuner:
             dgs = [G.csr(host_graphs[i].offsets, host_graphs[i].nbrs, host_graphs[i].n)
                    for i in reps_idx]
             best, times = autotune(dgs, CANDIDATES, self.reps)
-            self.table[key] = {"choice": CANDIDATES[best], "times_ms": times}
+            # then the workgroup shape for the chosen rule
+            shapes = [dict(CANDIDATES[best], block=b) for b in BLOCKS]
+            bbest, btimes = autotune(dgs, shapes, self.reps)
+            self.table[key] = {"choice": shapes[bbest], "times_ms": times,
+                               "block_times_ms": dict(zip(map(str, BLOCKS), btimes))}
         if self.table_path:
             with open(self.table_path, "w") as f:
                 json.dump(self.table, f, indent=1)
         return keys
+
+    def batch_block(self, keys: list, host_graphs: list) -> int:
+        """Workgroup shape for one batch launch: the tuned shape of the class
+        that holds the most edges (one launch has one shape)."""
+        edges = {}
+        for k, g in zip(keys, host_graphs):
+            edges[k] = edges.get(k, 0) + int(g.offsets[-1])
+        top = max(edges, key=edges.get)
+        return int(self.table[top]["choice"].get("block", 256))
 
     def classes_for(self, keys: list):
         """(class option list, per-graph class index) for cc_batch."""

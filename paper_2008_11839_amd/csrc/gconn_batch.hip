@@ -279,6 +279,8 @@ gconn_status check_batch(const gconn_batch* b) {
   if (b->m > 0) GCONN_TRY(check_device_ptr(b->nbrs, "batch.nbrs"));
   GCONN_TRY(check_device_ptr(b->vbase, "batch.vbase"));
   if (b->graph_class) GCONN_TRY(check_device_ptr(b->graph_class, "batch.graph_class"));
+  if (b->block != 0 && (b->block < 64 || b->block > 1024 || b->block % 64 != 0))
+    return fail(GCONN_EINVAL, "batch.block must be 0 or a multiple of 64 in [64, 1024]");
   return GCONN_OK;
 }
 
@@ -338,7 +340,7 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
   lc.hooks = stats ? &ctrl->stat_hooks : nullptr;
   lc.atomic_compress = 1;  // compression writes are CAS in the batch
   Ctrl* st = stats ? ctrl : nullptr;
-  const uint32_t n = b->n, G = b->num_graphs, block = 256;
+  const uint32_t n = b->n, G = b->num_graphs, block = b->block ? b->block : 256;
 
   GCONN_TRY(reset_ctrl_and_parents(ctrl, P, n, s));
   k_batch_tiles<<<grid_for(G, block), block, 0, s>>>(b->vbase, G, tiles);

@@ -63,7 +63,8 @@ class _Stats(ctypes.Structure):
 class _Batch(ctypes.Structure):
     _fields_ = [("num_graphs", ctypes.c_uint32), ("n", ctypes.c_uint32), ("m", ctypes.c_uint64),
                 ("offsets", ctypes.c_void_p), ("nbrs", ctypes.c_void_p), ("vbase", ctypes.c_void_p),
-                ("graph_class", ctypes.c_void_p)]
+                ("graph_class", ctypes.c_void_p), ("block", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class _ClassOptions(ctypes.Structure):

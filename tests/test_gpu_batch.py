@@ -64,7 +64,8 @@ def test_batch_labels_match_oracle_per_graph(batch_case):
     rng = np.random.default_rng(3)
     for ci, classes in enumerate(CLASS_SETS):
         gclass = rng.integers(0, len(classes), size=len(gs))
-        db = B.upload(hb, graph_class=gclass if len(classes) > 1 else None)
+        db = B.upload(hb, graph_class=gclass if len(classes) > 1 else None,
+                      block=(0, 512, 128)[ci % 3])
         say(f"[batch] graphs={len(gs)} n={hb.n} m={hb.m} class_set={ci}")
         for rep in range(3):
             lab, st = B.cc_batch(db, classes, stats=True)
@@ -97,10 +98,13 @@ def test_autotuner_choices_give_oracle_labels(batch_case, tmp_path):
     keys = tuner.tune(gs)
     assert len(keys) == len(gs) and len(tuner.table) >= 2
     for k, rec in tuner.table.items():
-        assert rec["choice"] in B.CANDIDATES and len(rec["times_ms"]) == len(B.CANDIDATES)
+        choice = dict(rec["choice"])
+        assert choice.pop("block") in B.BLOCKS and choice in B.CANDIDATES
+        assert len(rec["times_ms"]) == len(B.CANDIDATES)
+        assert len(rec["block_times_ms"]) == len(B.BLOCKS)
     classes, gclass = tuner.classes_for(keys)
     hb = B.concat(gs)
-    db = B.upload(hb, graph_class=gclass)
+    db = B.upload(hb, graph_class=gclass, block=tuner.batch_block(keys, gs))
     lab = B.cc_batch(db, classes)
     torch.cuda.synchronize()
     _check(hb, gs, want, lab)
@@ -116,6 +120,9 @@ def test_batch_rejects_bad_layouts(batch_case):
     gs, _ = batch_case
     db = B.upload(B.concat(gs[:3]))
     db.c.n = db.c.n - 1  # not a multiple of 64
+    with pytest.raises(G.GconnError):
+        B.cc_batch(db, [dict()])
+    db = B.upload(B.concat(gs[:3]), block=96)  # not a multiple of 64
     with pytest.raises(G.GconnError):
         B.cc_batch(db, [dict()])
     db = B.upload(B.concat(gs[:3]))
