@@ -570,6 +570,9 @@ def main() -> int:
                    "kout_prelink": args.kout_prelink, "atomic_compress": args.atomic_compress,
                    "parity_vs_oracle": parity},
         "roofline": roofline,
+        "context": {"note": "the paper's own numbers, other hardware and inputs: not targets",
+                    "paper_avg_static_speedup_over_prior_gpu_codes": 2.47,
+                    "paper_kron_g500_logn21_kout_async_gedges_per_s_v100": 357},
         "phases_ms": {k: round(v, 5) for k, v in phase_ms.items()},
         "event_ms_per_step": round(ev_ms, 5),
         "stats": st,
