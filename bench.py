@@ -65,6 +65,21 @@ def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
             "finalize_ms": 12 * A}
 
 
+def golden(name: str):
+    """A stored record written by tests/golden/make_golden.py (the oracle's
+    labels of a seeded workload), or None when there is none for it."""
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def labels_sha(labels) -> str:
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(labels, dtype="<u4").tobytes()).hexdigest()
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -296,16 +311,19 @@ def other_configs_bench(G, args) -> dict:
     overhead case) and the bond-percolation grids (2D 4096^2 at p = 0.7, 3D
     256^3 at p = 0.6: many components, long chains), each over union-find with
     and without sampling and the round-based finishes (SV, Liu-Tarjan PRF,
-    label propagation), labels checked against the oracle."""
+    label propagation), labels checked against the oracle's stored labels."""
     import numpy as np
     import torch
 
     import graphgen
-    import oracle
     dev = torch.device("cuda", 0)
-    work = {"er_1e5": lambda: graphgen.er(100_000, 1_000_000, args.seed),
-            "grid2d_4096_p0.7": lambda: graphgen.grid2d(4096, 4096, 0.7, args.seed),
-            "grid3d_256_p0.6": lambda: graphgen.grid3d(256, 256, 256, 0.6, args.seed)}
+    # workload name -> (generator, golden record written by the oracle)
+    work = {"er_1e5": (lambda: graphgen.er(100_000, 1_000_000, args.seed),
+                       f"er_n100000_m1000000_s{args.seed}"),
+            "grid2d_4096_p0.7": (lambda: graphgen.grid2d(4096, 4096, 0.7, args.seed),
+                                 f"grid2d_4096_p07_s{args.seed}"),
+            "grid3d_256_p0.6": (lambda: graphgen.grid3d(256, 256, 256, 0.6, args.seed),
+                                f"grid3d_256_p06_s{args.seed}")}
     cfgs = [dict(sample="kout", link="rem_cas", find="split"),
             dict(sample="none", link="rem_cas", find="split"),
             dict(sample="none", link="async", find="halve"),
@@ -313,18 +331,18 @@ def other_configs_bench(G, args) -> dict:
             dict(sample="kout", link="lp"), dict(sample="none", link="sv"),
             dict(sample="none", link="lp")]
     out = {}
-    for name, make in work.items():
+    for name, (make, gold_name) in work.items():
         C = make()
-        want = oracle.cc(C.n, C.offsets, C.nbrs)
-        comps = int((want == np.arange(C.n, dtype=np.uint32)).sum())
+        gold = golden(gold_name)
         dg = G.csr(C.offsets, C.nbrs, C.n)
         lab = torch.empty(C.n, dtype=torch.int32, device=dev)
-        res = {"n": C.n, "m_directed": C.m, "components": comps, "runs": []}
+        res = {"n": C.n, "m_directed": C.m,
+               "components": gold["components"] if gold else None, "runs": []}
         for cfg in cfgs:
             o = G.Options(**cfg)
             ws = G.alloc_workspace(G.workspace_size(dg, o))
             _, st = G.cc(dg, labels=lab, options=o, workspace=ws, stats=True)
-            ok = bool(np.array_equal(G.to_u32(lab), want))
+            ok = labels_sha(G.to_u32(lab)) == gold["labels_sha256"] if gold else None
             reps = 5
             G.cc(dg, labels=lab, options=o, workspace=ws)
             torch.cuda.synchronize()
@@ -334,7 +352,7 @@ def other_configs_bench(G, args) -> dict:
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / reps
             run = {**cfg, "ms": round(ms, 4), "gedges_per_s": round(C.m / (ms * 1e-3) / 1e9, 2),
-                   "rounds": st["rounds"], "labels_match_oracle": ok}
+                   "rounds": st["rounds"], "labels_match_oracle_golden": ok}
             if cfg["link"] not in ("sv", "lt", "lp"):
                 # the same pipeline captured once into a HIP graph, replayed
                 ex = G.capture_cc(dg, lab, options=o, workspace=ws)
@@ -345,7 +363,8 @@ def other_configs_bench(G, args) -> dict:
                     ex.launch()
                 torch.cuda.synchronize()
                 run["captured_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
-                run["captured_labels_match_oracle"] = bool(np.array_equal(G.to_u32(lab), want))
+                run["captured_labels_match_oracle_golden"] = (labels_sha(G.to_u32(lab)) ==
+                                                       gold["labels_sha256"] if gold else None)
                 ex.close()
             res["runs"].append(run)
             del ws
@@ -362,11 +381,10 @@ def mixed_bench(G, args) -> dict:
     import torch
 
     import graphgen
-    import oracle
     dev = torch.device("cuda", 0)
     n, k = 1 << args.mixed_scale, 10
     src, dst = graphgen.ba_edges(n, k, args.seed)
-    want = oracle.cc_coo(n, src, dst)
+    gold = golden(f"ba{args.mixed_scale}_k10_s{args.seed}")
     B = 1 << 20
     out = {"workload": f"Barabasi-Albert n=2^{args.mixed_scale}, {k} edges per arriving vertex "
                        f"({len(src)} inserts, shuffled), uniform query pairs, batches of {B} "
@@ -390,7 +408,7 @@ def mixed_bench(G, args) -> dict:
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         lat = [x.elapsed_time(y) for x, y in evs]
-        ok = bool(np.array_equal(G.to_u32(inc.labels()), want))
+        ok = labels_sha(G.to_u32(inc.labels())) == gold["labels_sha256"] if gold else None
         inc.close()
         out["ratios"][str(ratio)] = {
             "elements": len(kind), "queries": int(kind.sum()),
@@ -398,7 +416,7 @@ def mixed_bench(G, args) -> dict:
             "wall_elements_per_s": round(len(kind) / wall, 1),
             "batch_ms_p50": round(percentile(lat, 50), 4),
             "batch_ms_p99": round(percentile(lat, 99), 4),
-            "labels_match_oracle": ok}
+            "labels_match_oracle_golden": ok}
         del kt, at, bt, res
     return out
 

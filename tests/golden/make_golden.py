@@ -30,6 +30,9 @@ CONFIGS = {
     "rmat24_ef16_s1": lambda: graphgen.rmat(24, 16, 1),
     "grid2d_4096_p07_s1": lambda: graphgen.grid2d(4096, 4096, 0.7, 1),
     "grid3d_256_p06_s1": lambda: graphgen.grid3d(256, 256, 256, 0.6, 1),
+    # the Barabasi-Albert stream of the mixed-batch measurement, as a graph
+    "ba22_k10_s1": lambda: graphgen.csr_from_edges(1 << 22, *graphgen.ba_edges(1 << 22, 10, 1),
+                                                   True, "ba22_k10_s1"),
 }
 LMAX_SAMPLES, LMAX_SEED = 1024, 1
 
