@@ -561,6 +561,9 @@ def main() -> int:
             rec = json.load(f)
         if rec.get("source_sha") == source_sha() and rec.get("kernel") == PHASE_KERNEL[dominant]:
             traffic = rec.get("hbm_bytes_per_launch")
+    per_kernel_traffic = {}
+    if os.path.exists(tpath) and rec.get("source_sha") == source_sha():
+        per_kernel_traffic = rec.get("per_kernel_bytes", {})
 
     roofline = {
         "bound": "hbm", "kernel": PHASE_KERNEL[dominant],
@@ -592,6 +595,15 @@ def main() -> int:
                     "paper_avg_static_speedup_over_prior_gpu_codes": 2.47,
                     "paper_kron_g500_logn21_kout_async_gedges_per_s_v100": 357},
         "phases_ms": {k: round(v, 5) for k, v in phase_ms.items()},
+        # every phase against the same HBM peak: algorithmic bytes and, where
+        # the counters were taken for the current kernels, measured traffic
+        "phases_roofline": {
+            k: {"kernel": PHASE_KERNEL[k], "alg_bytes": abytes[k],
+                "alg_gbs": round(abytes[k] / (v * 1e-3) / 1e9, 1) if v > 0 else None,
+                "traffic": per_kernel_traffic.get(PHASE_KERNEL[k]),
+                "traffic_gbs": round(per_kernel_traffic[PHASE_KERNEL[k]] / (v * 1e-3) / 1e9, 1)
+                if v > 0 and PHASE_KERNEL[k] in per_kernel_traffic else None}
+            for k, v in phase_ms.items()},
         "event_ms_per_step": round(ev_ms, 5),
         "stats": st,
     }
