@@ -517,9 +517,14 @@ def main() -> int:
     log(f"stats {st} parity_vs_oracle_golden={parity}")
 
     # ------------------------------------------------------------ timed region
+    # The library's phase profiler brackets the sampling phase -- the dominant
+    # kernel -- of every timed step with two HIP events on the launch stream, so
+    # its duration for the roofline comes from the timed steps themselves.
     for _ in range(args.warmup):
         G.cc(dg, labels=labels, options=opts, workspace=ws)
     torch.cuda.synchronize()
+    G.profile_phases(["sample"])
+    G.profile_read(reset=True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
@@ -529,13 +534,16 @@ def main() -> int:
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    timed_ph = G.profile_read(reset=True)
+    G.profile_enable(False)
     ms_per_step = wall * 1e3 / args.steps
     ev_ms = ev0.elapsed_time(ev1) / args.steps
     value = m / (ms_per_step * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step wall, {ev_ms:.4f} ms/step events, "
         f"{value:.1f} Gedges/s")
+    timed_sample_ms = timed_ph["sample_ms"] / max(timed_ph["runs"], 1)
 
-    # ------------------------------------------------------------ per-phase HIP events
+    # ------------------------------------------------------------ every phase (after the timed region)
     G.profile_enable(True)
     G.profile_read(reset=True)
     for _ in range(args.steps):
@@ -550,6 +558,8 @@ def main() -> int:
         PHASE_KERNEL["sample_ms"] = "k_kout_prelink+k_kout_residual"
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     dom_ms = phase_ms[dominant]
+    if dominant == "sample_ms":
+        dom_ms = timed_sample_ms  # measured inside the timed region
     achieved = abytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
     total_alg = sum(abytes.values())
     log(f"phases (ms): {json.dumps({k: round(v, 4) for k, v in phase_ms.items()})}")

@@ -385,6 +385,9 @@ typedef struct gconn_phase_times {
   uint64_t runs;       /* pipeline runs accumulated                           */
 } gconn_phase_times;
 
+/* on: 0 off; 1 every phase; otherwise a mask of the phases to bracket, bit
+ * (p + 1) for the p-th field above (init = 0 ... finalize = 6), so a caller can
+ * time one kernel with two events per run. */
 gconn_status gconn_profile_enable(int on);
 /* Fills *out with the totals since the last reset; reset = 1 clears them. */
 gconn_status gconn_profile_read(gconn_phase_times* out, int reset);

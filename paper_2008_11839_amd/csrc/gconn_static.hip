@@ -1633,6 +1633,7 @@ gconn_status launch_query(const gconn_options& o, uint32_t* P, const uint32_t* a
 namespace {
 struct Profiler {
   bool on = false;
+  uint32_t mask = ~0u;  // bit p: bracket phase p
   struct Mark {
     int phase;
     hipEvent_t a, b;
@@ -1662,7 +1663,7 @@ thread_local Profiler g_prof;
 bool profiling() { return g_prof.on; }
 
 gconn_status prof_mark(int phase, bool begin, hipStream_t s) {
-  if (!g_prof.on) return GCONN_OK;
+  if (!g_prof.on || !((g_prof.mask >> phase) & 1u)) return GCONN_OK;
   hipEvent_t e = g_prof.get();
   if (!e) return fail(GCONN_EDEVICE, "hipEventCreate failed");
   GCONN_HIP(hipEventRecord(e, s));
@@ -1680,7 +1681,9 @@ void prof_count_run() {
 }
 
 gconn_status profile_enable(int on) {
+  if (on < 0) return fail(GCONN_EINVAL, "profile mask must be >= 0");
   g_prof.on = on != 0;
+  g_prof.mask = on == 1 ? ~0u : ((uint32_t)on >> 1);
   return GCONN_OK;
 }
 

@@ -445,6 +445,17 @@ def profile_enable(on: bool = True) -> None:
     _check(lib().gconn_profile_enable(int(on)))
 
 
+PHASES = ["init", "sample", "compress", "lmax", "gather", "finish", "finalize"]
+
+
+def profile_phases(names) -> None:
+    """Profile only the named phases (two HIP events per phase per run)."""
+    mask = 0
+    for nm in names:
+        mask |= 1 << (PHASES.index(nm) + 1)
+    _check(lib().gconn_profile_enable(mask))
+
+
 def profile_read(reset: bool = True) -> dict:
     t = _PhaseTimes()
     _check(lib().gconn_profile_read(ctypes.byref(t), int(reset)))
