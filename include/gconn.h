@@ -139,7 +139,11 @@ typedef struct gconn_options {
   int32_t schedule;      /* k-out kernel shape: 0 persistent lanes with the next
                             vertex's row prefetched (default), 1 one lane per
                             vertex, 2 lane-refill step machine (Union-Rem-CAS,
-                            first-k, uint32 offsets; else as 0)            (0) */
+                            first-k, uint32 offsets; else as 0), 3 two-stage
+                            pipeline: the next vertex's neighbour parents
+                            loaded during the current unions (Union-Rem-CAS
+                            with SplitAtomicOne / HalveAtomicOne, first k <= 2;
+                            else as 0)                                      (0) */
   int32_t atomic_compress; /* path-compression and splice writes (FindSplit,
                             FindHalve, SplitAtomicOne, HalveAtomicOne, the
                             Union-Early splice): 1 CAS as in the atomic rules,

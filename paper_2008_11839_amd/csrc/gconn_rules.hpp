@@ -269,9 +269,12 @@ GCONN_HD bool union_early(const LinkCtx& c, uint32_t u, uint32_t v) {
 // read, which the argument above already allows for; the hook itself is a CAS
 // that validates r_u is still a root.
 template <int F, int S>
-GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v) {
+GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu = kEmpty,
+                            uint32_t pv = kEmpty) {
+  // pu, pv: values P[u], P[v] are known to have held (a caller that loaded
+  // them ahead of time); kEmpty reads them here.
   uint32_t ru = u, rv = v;
-  uint32_t pru = ld(&c.P[ru]), prv = ld(&c.P[rv]);
+  uint32_t pru = pu != kEmpty ? pu : ld(&c.P[ru]), prv = pv != kEmpty ? pv : ld(&c.P[rv]);
   for (;;) {
     if (pru == prv) return false;
     if (pru < prv) {
@@ -447,6 +450,14 @@ struct Rule {
     else if constexpr (U == kUnionRemLock) return union_rem_lock<F, S>(c, u, v);
     else if constexpr (S == kSpliceAtomic) return union_rem_splice<F>(c, u, v);
     else return union_rem_cas<F, S>(c, u, v);
+  }
+  // The same union, given parent values of u and v loaded ahead of time (any
+  // value a slot has held is an ancestor, so a stale one is a valid start).
+  // Only Union-Rem-CAS (SplitAtomicOne / HalveAtomicOne) uses them.
+  GCONN_HD static bool unite_from(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu,
+                                  uint32_t pv) {
+    if constexpr (U == kUnionRemCas && S != kSpliceAtomic) return union_rem_cas<F, S>(c, u, v, pu, pv);
+    else return unite(c, u, v);
   }
 };
 

@@ -196,6 +196,64 @@ __global__ void k_sample_kout_pf(const OffT* __restrict__ off, const uint32_t* _
   }
 }
 
+// Two-stage pipelined k-out for Union-Rem-CAS (first k <= 2 edges): while a
+// lane runs the unions of its vertex v, the parent entries of the next
+// vertex and of its two sampled neighbours are already in flight, and so is
+// the row of the vertex after that.  The unions start from those values: a
+// parent value loaded earlier is one the slot has held, so it is an ancestor
+// and a valid starting point; the hook CAS re-validates any root it acts on.
+template <class R, typename OffT>
+__global__ void k_sample_kout_pipe(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                                   uint32_t n, uint32_t k, LinkCtx lc, Ctrl* stats) {
+  const uint64_t T = wave_stride();
+  const uint32_t* P = lc.P;
+  // row of x: number of sampled entries and the first two (0 when absent:
+  // P[0] is a valid address and its value is then ignored)
+  auto row = [&](uint64_t x, uint32_t& t, uint32_t& a, uint32_t& b) {
+    t = 0;
+    a = 0;
+    b = 0;
+    if (x >= n) return;
+    const uint64_t s = off[x], d = (uint64_t)off[x + 1] - s;
+    t = (uint32_t)(d < k ? d : k);
+    if (t > 0) a = nbrs[s];
+    if (t > 1) b = nbrs[s + 1];
+  };
+  uint64_t v = gtid();
+  uint32_t t, w0, w1;
+  row(v, t, w0, w1);
+  uint32_t p0 = ld(&P[w0]), p1 = ld(&P[w1]);
+  uint32_t nt, n0, n1;
+  row(v + T, nt, n0, n1);
+  unsigned long long sampled = 0;
+  while (v < n) {
+    const uint64_t nv = v + T;
+    // stage 2 for the next vertex, stage 1 for the one after
+    const uint32_t q0 = ld(&P[n0]), q1 = ld(&P[n1]);
+    uint32_t mt, m0, m1;
+    row(nv + T, mt, m0, m1);
+    if (t > 0) {
+      R::unite_from(lc, (uint32_t)v, w0, kEmpty, p0);
+      if (t > 1) R::unite_from(lc, (uint32_t)v, w1, kEmpty, p1);
+      sampled += t;
+    }
+    v = nv;
+    t = nt;
+    w0 = n0;
+    w1 = n1;
+    p0 = q0;
+    p1 = q1;
+    nt = mt;
+    n0 = m0;
+    n1 = m1;
+  }
+  if (stats) {
+    // lanes leave the loop at different iterations; they have reconverged here
+    sampled = wave_sum(sampled);
+    if (lane() == 0 && sampled) atomicAdd(&stats->stat_sampled, sampled);
+  }
+}
+
 // k-out pre-link (first k <= 2 edges).  Runs before any union: every vertex v
 // is still a root and this lane is the only writer of P[v], so linking v under
 // its smallest sampled neighbour u < v is a plain store (it is a link of the
@@ -1346,6 +1404,16 @@ struct Run {
           kern<<<grid, 256, 0, s>>>(static_cast<const uint32_t*>(g.offsets), g.nbrs, n, o.k,
                                     link_ctx(), st);
           GCONN_LAUNCHED("k_sample_kout_rem_sm");
+          return GCONN_OK;
+        }));
+      } else if (o.schedule == 3 && o.link == GCONN_LINK_REM_CAS &&
+                 o.splice != GCONN_SPLICE_ATOMIC && !o.kout_random && o.k <= 2) {
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          const uint32_t grid =
+              contention_grid(persistent_grid(k_sample_kout_pipe<R, OffT>, block), n);
+          k_sample_kout_pipe<R, OffT><<<grid, block, 0, s>>>(off, g.nbrs, n, o.k, link_ctx(), st);
+          GCONN_LAUNCHED("k_sample_kout_pipe");
           return GCONN_OK;
         }));
       } else if (o.schedule == 1) {

@@ -331,7 +331,7 @@ def test_kout_rem_cas_schedules_agree(cases):
             _, e_s = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
             for find in ("naive", "split", "halve"):
                 for splice in ("split_one", "halve_one"):
-                    for sched in ("auto", "lane", "step"):
+                    for sched in ("auto", "lane", "step", "pipe"):
                         say(f"[sched] graph={name} k={k} find={find} splice={splice} sched={sched}")
                         o = G.Options(sample="kout", link="rem_cas", find=find, splice=splice,
                                       k=k, schedule=sched)
@@ -350,7 +350,7 @@ def test_hooks_count_is_n_minus_c_with_sampling(cases):
     from paper_2008_11839_amd import gconn as G
     for name, (C, dg, want) in cases.items():
         c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
-        for sched in ("auto", "lane", "step"):
+        for sched in ("auto", "lane", "step", "pipe"):
             lab, st = G.cc(dg, options=G.Options(sample="kout", link="rem_cas", schedule=sched),
                            stats=True)
             assert st["hooks"] == C.n - c, (name, sched)
