@@ -163,7 +163,7 @@ typedef struct gconn_options {
 typedef struct gconn_stats {
   uint64_t sampled_edges;   /* neighbour entries read by the sampling phase     */
   uint64_t active_vertices; /* vertices gathered for the finish (label != L_max) */
-  uint64_t finish_edges;    /* neighbour entries read by the finish (per round 1) */
+  uint64_t finish_edges;    /* neighbour entries read by the finish (SV/LT/LP: first round) */
   uint64_t hooks;           /* successful root links (union-find rules)         */
   uint64_t rounds;          /* SV / LT / LP rounds, or BFS levels               */
   uint32_t lmax;            /* most frequent sampled label (0xFFFFFFFF: none)   */
