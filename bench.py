@@ -215,6 +215,14 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
         lat = [(r["done_us"] - r["submit_us"]) / 1e3 for r in recs]
         return wall, lat, recs
 
+    def by_kind(lat):
+        q = [x for x, (k, _, _) in zip(lat, host) if k == 1]
+        i = [x for x, (k, _, _) in zip(lat, host) if k == 0]
+        return {"query_latency_ms_p50": round(percentile(q, 50), 3),
+                "query_latency_ms_p99": round(percentile(q, 99), 3),
+                "insert_latency_ms_p50": round(percentile(i, 50), 3),
+                "insert_latency_ms_p99": round(percentile(i, 99), 3)}
+
     wall, lat, recs = run(None)
     sat_rate = len(host) / wall
     out = {"saturated": {"updates_per_s": round(updates / wall, 1),
@@ -225,7 +233,7 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
         wall, lat, recs = run(rho * sat_rate)
         out[f"load_{rho}"] = {"updates_per_s": round(updates / wall, 1),
                               "latency_ms_p50": round(percentile(lat, 50), 3),
-                              "latency_ms_p99": round(percentile(lat, 99), 3)}
+                              "latency_ms_p99": round(percentile(lat, 99), 3), **by_kind(lat)}
     out["updates"], out["queries"] = updates, queries
     return out
 
