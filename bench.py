@@ -37,6 +37,25 @@ PHASE_KERNEL = {"init_ms": "k_init", "sample_ms": "k_sample_kout_pf", "lmax_ms":
                 "finalize_ms": "k_finalize"}
 
 
+def sample_kernels(args) -> str:
+    """The kernel(s) of the k-out sampling phase for these options."""
+    if args.kout_local or args.schedule == "twopass":
+        return "k_kout_local+k_kout_residual"
+    if args.kout_prelink:
+        return "k_kout_prelink+k_kout_residual"
+    return {"auto": "k_sample_kout_pf", "lane": "k_sample_kout", "pipe": "k_sample_kout_pipe",
+            "step": "k_sample_kout_rem_sm"}[args.schedule]
+
+
+def kernel_traffic(per_kernel: dict, name: str):
+    """Measured bytes of a kernel, or of '+'-joined kernels summed (None if any
+    part was not measured)."""
+    parts = name.split("+")
+    if not all(p in per_kernel for p in parts):
+        return None
+    return sum(per_kernel[p] for p in parts)
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -443,6 +462,10 @@ def main() -> int:
     ap.add_argument("--splice", default="split_one")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--kout-prelink", type=int, default=0, choices=(0, 1))
+    ap.add_argument("--kout-local", type=int, default=0, choices=(0, 1))
+    ap.add_argument("--schedule", default="twopass", choices=("auto", "lane", "step", "pipe", "twopass"),
+                    help="k-out kernel schedule (twopass: rows streamed to a slot array, then "
+                         "the union pass over the slots)")
     ap.add_argument("--atomic-compress", type=int, default=1, choices=(0, 1))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -495,6 +518,7 @@ def main() -> int:
     torch.cuda.synchronize()
     opts = G.Options(sample=args.sample, link=args.link, find=args.find, splice=args.splice,
                      block=args.block, kout_prelink=bool(args.kout_prelink),
+                     kout_local=bool(args.kout_local), schedule=args.schedule,
                      atomic_compress=bool(args.atomic_compress))
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ws = G.alloc_workspace(G.workspace_size(dg, opts))
@@ -562,8 +586,8 @@ def main() -> int:
     runs = max(ph.pop("runs"), 1)
     phase_ms = {k: v / runs for k, v in ph.items() if k in PHASE_KERNEL}
     abytes = algorithmic_bytes(n, m, st, opts.lmax_samples)
-    if args.kout_prelink and args.sample == "kout":
-        PHASE_KERNEL["sample_ms"] = "k_kout_prelink+k_kout_residual"
+    if args.sample == "kout":
+        PHASE_KERNEL["sample_ms"] = sample_kernels(args)
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
     dom_ms = phase_ms[dominant]
     if dominant == "sample_ms":
@@ -577,8 +601,8 @@ def main() -> int:
     if os.path.exists(tpath):
         with open(tpath) as f:
             rec = json.load(f)
-        if rec.get("source_sha") == source_sha() and rec.get("kernel") == PHASE_KERNEL[dominant]:
-            traffic = rec.get("hbm_bytes_per_launch")
+        if rec.get("source_sha") == source_sha():
+            traffic = kernel_traffic(rec.get("per_kernel_bytes", {}), PHASE_KERNEL[dominant])
     per_kernel_traffic = {}
     if os.path.exists(tpath) and rec.get("source_sha") == source_sha():
         per_kernel_traffic = rec.get("per_kernel_bytes", {})
@@ -606,7 +630,8 @@ def main() -> int:
                                f"scrambled ids, symmetrised CSR, seed {args.seed}",
                    "n": n, "m_directed": m, "sample": args.sample, "link": args.link,
                    "find": args.find, "splice": args.splice, "block": args.block,
-                   "kout_prelink": args.kout_prelink, "atomic_compress": args.atomic_compress,
+                   "kout_prelink": args.kout_prelink, "kout_local": args.kout_local,
+                   "schedule": args.schedule, "atomic_compress": args.atomic_compress,
                    "parity_vs_oracle": parity},
         "roofline": roofline,
         "context": {"note": "the paper's own numbers, other hardware and inputs: not targets",
@@ -618,9 +643,10 @@ def main() -> int:
         "phases_roofline": {
             k: {"kernel": PHASE_KERNEL[k], "alg_bytes": abytes[k],
                 "alg_gbs": round(abytes[k] / (v * 1e-3) / 1e9, 1) if v > 0 else None,
-                "traffic": per_kernel_traffic.get(PHASE_KERNEL[k]),
-                "traffic_gbs": round(per_kernel_traffic[PHASE_KERNEL[k]] / (v * 1e-3) / 1e9, 1)
-                if v > 0 and PHASE_KERNEL[k] in per_kernel_traffic else None}
+                "traffic": kernel_traffic(per_kernel_traffic, PHASE_KERNEL[k]),
+                "traffic_gbs": round(kernel_traffic(per_kernel_traffic, PHASE_KERNEL[k]) /
+                                     (v * 1e-3) / 1e9, 1)
+                if v > 0 and kernel_traffic(per_kernel_traffic, PHASE_KERNEL[k]) else None}
             for k, v in phase_ms.items()},
         "event_ms_per_step": round(ev_ms, 5),
         "stats": st,

@@ -143,7 +143,11 @@ typedef struct gconn_options {
                             pipeline: the next vertex's neighbour parents
                             loaded during the current unions (Union-Rem-CAS
                             with SplitAtomicOne / HalveAtomicOne, first k <= 2;
-                            else as 0)                                      (0) */
+                            else as 0), 4 two passes: a streaming pass writes
+                            every vertex's sampled neighbours to a slot array,
+                            then the union pass runs over the slots, so its
+                            lanes start on unions at once (first k <= 2; else
+                            as 0)                                           (0) */
   int32_t atomic_compress; /* path-compression and splice writes (FindSplit,
                             FindHalve, SplitAtomicOne, HalveAtomicOne, the
                             Union-Early splice): 1 CAS as in the atomic rules,
@@ -156,6 +160,13 @@ typedef struct gconn_options {
                             own slot), and sends only its other sampled edge(s)
                             through the union rule; 0 unites every sampled edge.
                             Same partition either way.                     (0) */
+  int32_t kout_local;    /* first-k k-out with k <= 2: 1 unites, in LDS, the
+                            sampled edges whose endpoints both lie in the same
+                            8192-vertex id range (one workgroup per range), and
+                            sends only the edges leaving a range through the
+                            union rule -- for graphs whose ids are local, such
+                            as grids and meshes.  Same partition.  Overrides
+                            kout_prelink.                                   (0) */
 } gconn_options;
 
 /* Counters filled when a stats pointer is passed (the call then synchronises

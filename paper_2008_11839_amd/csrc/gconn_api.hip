@@ -52,11 +52,13 @@ gconn_status check_options(const gconn_options& o) {
   if (o.hb_n < 1 || o.hb_n > 1024) return fail(GCONN_EINVAL, "options.hb_n must be in [1, 1024]");
   if (o.lmax_samples < 1 || o.lmax_samples > kMaxLmaxSamples)
     return fail(GCONN_EINVAL, "options.lmax_samples must be in [1, 4096]");
-  if (o.schedule < 0 || o.schedule > 3) return fail(GCONN_EINVAL, "options.schedule out of range");
+  if (o.schedule < 0 || o.schedule > 4) return fail(GCONN_EINVAL, "options.schedule out of range");
   if (o.atomic_compress != 0 && o.atomic_compress != 1)
     return fail(GCONN_EINVAL, "options.atomic_compress must be 0 or 1");
   if (o.kout_prelink != 0 && o.kout_prelink != 1)
     return fail(GCONN_EINVAL, "options.kout_prelink must be 0 or 1");
+  if (o.kout_local != 0 && o.kout_local != 1)
+    return fail(GCONN_EINVAL, "options.kout_local must be 0 or 1");
   if (o.block < 64 || o.block > 1024 || (o.block % 64) != 0)
     return fail(GCONN_EINVAL, "options.block must be a multiple of 64 in [64, 1024]");
   return GCONN_OK;
@@ -216,6 +218,7 @@ void gconn_options_default(gconn_options* o) {
   o->schedule = 0;
   o->atomic_compress = 1;
   o->kout_prelink = 0;
+  o->kout_local = 0;
 }
 
 gconn_status gconn_workspace_size(const gconn_graph* g, const gconn_options* opt, int want_forest,

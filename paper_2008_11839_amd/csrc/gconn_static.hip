@@ -304,6 +304,88 @@ __global__ void k_kout_prelink(const OffT* __restrict__ off, const uint32_t* __r
   }
 }
 
+// Local-first k-out (first k <= 2 edges).  Workgroup r owns the id range
+// [r * kLocalRange, (r + 1) * kLocalRange): it unites the sampled edges with
+// both endpoints in the range on a copy of the range's parents in LDS (LDS
+// atomics: far cheaper than device atomics, and the range's trees never
+// leave the CU), linking the larger local root under the smaller, so each
+// local root is its local component's minimum.  It then writes every vertex's
+// local root to P (a flat local forest) and sends the sampled edges that
+// leave the range to res[v] for the union pass.  Runs on a freshly
+// initialised P; the partition after both passes is the sampled one.  With
+// local == 0 it only streams the rows: every sampled edge goes to res[v] and
+// the union pass does all the linking (the two-pass schedule).
+constexpr uint32_t kLocalRange = 8192;
+
+__device__ __forceinline__ uint32_t lds_root(uint32_t* L, uint32_t x) {
+  for (;;) {
+    const uint32_t p = __hip_atomic_load(&L[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+template <typename OffT>
+__global__ void __launch_bounds__(512) k_kout_local(const OffT* __restrict__ off,
+                                                    const uint32_t* __restrict__ nbrs,
+                                                    uint32_t n, uint32_t k, uint32_t* P, uint2* res,
+                                                    uint32_t* fu, uint32_t* fv, int local,
+                                                    Ctrl* stats) {
+  __shared__ uint32_t L[kLocalRange];
+  const uint64_t lo = (uint64_t)blockIdx.x * kLocalRange;
+  const uint32_t len = (uint32_t)min<uint64_t>(kLocalRange, n - lo);
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) L[i] = i;
+  __syncthreads();
+  unsigned long long sampled = 0, linked = 0;
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const uint64_t v = lo + i;
+    const uint64_t b = off[v], d = (uint64_t)off[v + 1] - b;
+    const uint32_t t = (uint32_t)(d < k ? d : k);
+    sampled += t;
+    uint2 r = make_uint2(kEmpty, kEmpty);
+    for (uint32_t j = 0; j < t; ++j) {
+      const uint32_t w = nbrs[b + j];
+      if (!local || w < lo || w >= lo + len) {  // leaves the range: global union pass
+        if (j == 0) r.x = w;
+        else r.y = w;
+        continue;
+      }
+      // local union of i and w - lo (min-linking, CAS on the larger root)
+      uint32_t a = lds_root(L, i), c = lds_root(L, (uint32_t)(w - lo));
+      while (a != c) {
+        const uint32_t hi = a > c ? a : c, low = a > c ? c : a;
+        uint32_t e = hi;
+        if (__hip_atomic_compare_exchange_strong(&L[hi], &e, low, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+          ++linked;
+          if (fu) {
+            fu[lo + hi] = (uint32_t)v;
+            fv[lo + hi] = w;
+          }
+          break;
+        }
+        a = lds_root(L, e);
+        c = lds_root(L, low);
+      }
+    }
+    res[v] = r;
+  }
+  __syncthreads();
+  if (local)
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+      const uint32_t r = lds_root(L, i);
+      if (r != i) P[lo + i] = (uint32_t)lo + r;
+    }
+  if (stats) {
+    sampled = wave_sum(sampled);
+    linked = wave_sum(linked);
+    if (lane() == 0) {
+      if (sampled) atomicAdd(&stats->stat_sampled, sampled);
+      if (linked) atomicAdd(&stats->stat_hooks, linked);
+    }
+  }
+}
+
 // Union pass over the residual sampled edges of the pre-link.
 template <class R>
 __global__ void k_kout_residual(const uint2* __restrict__ res, uint32_t n, LinkCtx lc) {
@@ -1216,8 +1298,15 @@ namespace {
 constexpr uint32_t kPersistentBlocks = 2048;  // round kernels: 256 CUs x 8 workgroups
 
 // The k-out pre-link covers first-k sampling with k <= 2.
+// The slot-array k-out passes (k_kout_local, then k_kout_residual): the LDS
+// local-first variant, or the plain two-pass schedule.
+bool kout_local_applies(const gconn_options& o) {
+  return (o.kout_local || o.schedule == 4) && o.sample == GCONN_SAMPLE_KOUT && !o.kout_random &&
+         o.k <= 2;
+}
 bool kout_prelink_applies(const gconn_options& o) {
-  return o.kout_prelink && o.sample == GCONN_SAMPLE_KOUT && !o.kout_random && o.k <= 2;
+  return !kout_local_applies(o) && o.kout_prelink && o.sample == GCONN_SAMPLE_KOUT &&
+         !o.kout_random && o.k <= 2;
 }
 
 template <class Fn>
@@ -1385,7 +1474,19 @@ struct Run {
     Ctrl* st = want_stats ? ctrl : nullptr;
     GCONN_TRY(prof_mark(kPhaseSample, true, s));
     if (o.sample == GCONN_SAMPLE_KOUT) {
-      if (kout_prelink_applies(o)) {
+      if (kout_local_applies(o)) {
+        uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
+        const uint32_t ranges = (uint32_t)((n + kLocalRange - 1) / kLocalRange);
+        k_kout_local<OffT><<<ranges, 512, 0, s>>>(off, g.nbrs, n, o.k, P, res, fu, fv,
+                                                  o.kout_local ? 1 : 0, st);
+        GCONN_LAUNCHED("k_kout_local");
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n, link_ctx());
+          GCONN_LAUNCHED("k_kout_residual");
+          return GCONN_OK;
+        }));
+      } else if (kout_prelink_applies(o)) {
         uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
         const uint32_t pgrid = std::min<uint32_t>(gridN(n), 8192);
         k_kout_prelink<OffT><<<pgrid, block, 0, s>>>(off, g.nbrs, n, o.k, P, res, fu, fv, st);
@@ -1858,7 +1959,7 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
     L.segs = take(8 * L.seg_cap);
   }
   if (needs_claims(o.link)) L.hooks = take(4 * n);
-  if (csr && kout_prelink_applies(o)) L.resid = take(8 * n);
+  if (csr && (kout_prelink_applies(o) || kout_local_applies(o))) L.resid = take(8 * n);
   const bool iterative =
       o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
   if (iterative) {

@@ -23,7 +23,7 @@ LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt
         "afforest": 8, "rem_lock": 9}
 FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3}
 SPLICE = {"split_one": 0, "halve_one": 1, "splice_atomic": 2}
-SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3}
+SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3, "twopass": 4}
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
                "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]
 STATUS = {0: "GCONN_OK", -1: "GCONN_EINVAL", -2: "GCONN_ENOMEM", -3: "GCONN_EDEVICE",
@@ -50,7 +50,8 @@ class _Options(ctypes.Structure):
                 ("lmax_samples", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("kout_random", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("atomic_compress", ctypes.c_int32), ("kout_prelink", ctypes.c_int32)]
+                ("atomic_compress", ctypes.c_int32), ("kout_prelink", ctypes.c_int32),
+                ("kout_local", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -203,6 +204,7 @@ class Options:
     schedule: str = "auto"
     atomic_compress: bool = True
     kout_prelink: bool = False
+    kout_local: bool = False
 
     def to_c(self) -> _Options:
         o = _Options()
@@ -220,6 +222,7 @@ class Options:
         o.schedule = SCHEDULE[self.schedule]
         o.atomic_compress = int(self.atomic_compress)
         o.kout_prelink = int(self.kout_prelink)
+        o.kout_local = int(self.kout_local)
         return o
 
 

@@ -25,6 +25,8 @@ WORK = {"rmat24_ef16_s1": lambda: graphgen.rmat(24, 16, 1),
         "grid3d_256_p06_s1": lambda: graphgen.grid3d(256, 256, 256, 0.6, 1)}
 CONFIGS = [dict(sample="kout", link="rem_cas", find="split", splice="split_one"),  # benchmark
            dict(sample="kout", link="rem_cas", find="halve", kout_prelink=True),
+           dict(sample="kout", link="rem_cas", find="split", kout_local=True),
+           dict(sample="kout", link="rem_cas", find="split", schedule="twopass"),
            dict(sample="kout", link="async", find="split"),
            dict(sample="hb", link="async", find="split"),
            dict(sample="none", link="rem_cas", find="split"),

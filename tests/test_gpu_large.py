@@ -45,7 +45,7 @@ def rmat22(gpu_available):
     return C, G.csr(C.offsets, C.nbrs, C.n), want
 
 
-@pytest.mark.parametrize("prelink", [False, True])
+@pytest.mark.parametrize("prelink", [False, True, "local", "twopass"])
 @pytest.mark.parametrize("ac", [True, False])
 def test_rmat22_labels_match_oracle(rmat22, ac, prelink):
     import torch
@@ -55,7 +55,9 @@ def test_rmat22_labels_match_oracle(rmat22, ac, prelink):
     for cfg in CONFIGS:
         if prelink and cfg["sample"] != "kout":
             continue
-        o = G.Options(atomic_compress=ac, kout_prelink=prelink, **cfg)
+        o = G.Options(atomic_compress=ac, kout_prelink=prelink is True,
+                      kout_local=prelink == "local",
+                      schedule="twopass" if prelink == "twopass" else "auto", **cfg)
         ws = G.alloc_workspace(G.workspace_size(dg, o))
         for rep in range(3):
             say(f"[rmat22] {cfg} atomic_compress={ac} prelink={prelink} rep={rep}")

@@ -331,7 +331,7 @@ def test_kout_rem_cas_schedules_agree(cases):
             _, e_s = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
             for find in ("naive", "split", "halve"):
                 for splice in ("split_one", "halve_one"):
-                    for sched in ("auto", "lane", "step", "pipe"):
+                    for sched in ("auto", "lane", "step", "pipe", "twopass"):
                         say(f"[sched] graph={name} k={k} find={find} splice={splice} sched={sched}")
                         o = G.Options(sample="kout", link="rem_cas", find=find, splice=splice,
                                       k=k, schedule=sched)
@@ -350,7 +350,7 @@ def test_hooks_count_is_n_minus_c_with_sampling(cases):
     from paper_2008_11839_amd import gconn as G
     for name, (C, dg, want) in cases.items():
         c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
-        for sched in ("auto", "lane", "step", "pipe"):
+        for sched in ("auto", "lane", "step", "pipe", "twopass"):
             lab, st = G.cc(dg, options=G.Options(sample="kout", link="rem_cas", schedule=sched),
                            stats=True)
             assert st["hooks"] == C.n - c, (name, sched)
@@ -366,6 +366,38 @@ def test_random_kout_and_larger_k(cases):
                         got = _labels(G, dg, sample="kout", k=k, kout_random=random, link=link,
                                       schedule=sched, seed=7)
                         assert np.array_equal(got, want), (name, k, random, link, sched)
+
+
+def test_kout_local(cases):
+    """k-out with the LDS local-first pass: labels, sampled-edge count, L_max,
+    active set and hook count equal the oracle's; the spanning forest is valid
+    and fills exactly the non-minimum slots (local links record their edge)."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    for name, (C, dg, want) in cases.items():
+        c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
+        roots_mask = want != np.arange(C.n, dtype=np.uint32)
+        for k in (1, 2):
+            s_lab, e = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
+            L = oracle.lmax(s_lab, 1024, 1)
+            for link, find, splice in UF_RULES:
+                say(f"[local] graph={name} k={k} link={link} find={find} splice={splice}")
+                o = G.Options(sample="kout", link=link, find=find, splice=splice, k=k,
+                              kout_local=True)
+                lab, st = G.cc(dg, options=o, stats=True)
+                assert np.array_equal(G.to_u32(lab), want), (name, k, link, find, splice)
+                if C.m:
+                    assert st["sampled_edges"] == e
+                    assert st["lmax"] == L
+                    assert st["active_vertices"] == oracle.active_count(C.n, C.offsets, s_lab, L)
+                if link != "ecl":
+                    assert st["hooks"] == C.n - c, (name, k, link)
+                if link != "ecl" and splice != "splice_atomic":
+                    fu, fv, _ = G.spanning_forest(dg, want_labels=False, options=o)
+                    torch.cuda.synchronize()
+                    fu, fv = G.to_u32(fu), G.to_u32(fv)
+                    oracle.check_forest(C.n, C.offsets, C.nbrs, fu, fv, want)
+                    assert np.array_equal(fu != G.EMPTY, roots_mask), (name, k, link)
 
 
 def test_kout_prelink(cases):
