@@ -84,6 +84,67 @@ def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
             "finalize_ms": 12 * A}
 
 
+def jtb_bytes(n: int, st: dict) -> int:
+    """Algorithmic bytes of the Union-JTB pipeline (8-byte (rank, parent) words).
+
+    init: write W (8n).  k-out: offsets (4n) and, per sampled entry, the
+    neighbour id plus two words (20 B).  flatten: read W, write the roots (12n).
+    gather: offsets (4n), the roots when sampled (4n), the list (4A).  finish:
+    offsets of the active vertices (8A) and 20 B per entry.  links: one 8-byte
+    CAS per hook (8H).  canonical labels: roots (read W, write labels and M:
+    16n), minima (read labels: 4n), relabel (read labels, gather M, write: 12n).
+    """
+    Es, A, Ef, H = (st["sampled_edges"], st["active_vertices"], st["finish_edges"],
+                    st["hooks"])
+    base = 8 * n + 20 * Ef + 12 * A + 8 * H + 32 * n + 4 * n
+    if Es:
+        base += 4 * n + 20 * Es + 12 * n + 4 * n
+    return base
+
+
+def finish_rules_bench(G, args, dg, n: int, m: int, gold_sha) -> dict:
+    """The union-find design space on the headline graph: each finish rule
+    with k-out sampling and without, timed per call (labels checked against
+    the oracle's stored labels), with the whole pipeline's algorithmic bytes
+    and the fraction of the HBM roofline they imply."""
+    import torch
+    dev = torch.device("cuda", 0)
+    cfgs = [dict(link="rem_cas", find="split", splice="split_one"),
+            dict(link="async", find="halve"), dict(link="async", find="split"),
+            dict(link="early", find="halve"), dict(link="hooks", find="split"),
+            dict(link="rem_lock", find="split"), dict(link="ecl"), dict(link="afforest"),
+            dict(link="jtb", find="naive"), dict(link="jtb", find="two_try_split")]
+    lab = torch.empty(n, dtype=torch.int32, device=dev)
+    runs = []
+    for sample in ("kout", "none"):
+        for cfg in cfgs:
+            o = G.Options(sample=sample, **cfg)
+            ws = G.alloc_workspace(G.workspace_size(dg, o))
+            _, st = G.cc(dg, labels=lab, options=o, workspace=ws, stats=True)
+            ok = labels_sha(G.to_u32(lab)) == gold_sha if gold_sha else None
+            reps = 5
+            G.cc(dg, labels=lab, options=o, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                G.cc(dg, labels=lab, options=o, workspace=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            if cfg["link"] == "jtb":
+                b = jtb_bytes(n, st)
+            else:
+                b = sum(algorithmic_bytes(n, m, st, o.lmax_samples).values())
+            run = {"sample": sample, **cfg, "ms": round(ms, 4),
+                   "gedges_per_s": round(m / (ms * 1e-3) / 1e9, 2), "alg_bytes": int(b),
+                   "roofline_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "hooks": st["hooks"], "labels_match_oracle_golden": ok}
+            runs.append(run)
+            log(f"finish rule {run}")
+            del ws
+    return {"workload": "the headline RMAT graph (already resident), one gconn_cc call per "
+                        "step, default options otherwise", "runs": runs}
+
+
 def golden(name: str):
     """A stored record written by tests/golden/make_golden.py (the oracle's
     labels of a seeded workload), or None when there is none for it."""
@@ -475,6 +536,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-rules", action="store_true",
+                    help="skip the union-find design-space sweep on the headline graph")
     ap.add_argument("--no-configs", action="store_true", help="skip the ER and grid workloads")
     ap.add_argument("--mixed-scale", type=int, default=22,
                     help="Barabasi-Albert stream of 2^scale vertices, 10 edges each")
@@ -543,9 +606,11 @@ def main() -> int:
     got_sha = hashlib.sha256(np.ascontiguousarray(got, dtype="<u4").tobytes()).hexdigest()
     golden_path = os.path.join(ROOT, "tests", "golden", f"{C.name}.json")
     parity = None
+    gold_sha = None
     if os.path.exists(golden_path):
         with open(golden_path) as f:
-            parity = json.load(f)["labels_sha256"] == got_sha
+            gold_sha = json.load(f)["labels_sha256"]
+        parity = gold_sha == got_sha
     log(f"stats {st} parity_vs_oracle_golden={parity}")
 
     # ------------------------------------------------------------ timed region
@@ -681,6 +746,10 @@ def main() -> int:
                                      "forest_edges": filled, "n_minus_c": n - comps}
         log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")
         del fu, fv, ws_f
+
+    # ------------------------------------------------------------ union-find design space
+    if not args.no_extras and not args.no_rules:
+        result["finish_rules"] = finish_rules_bench(G, args, dg, n, m, gold_sha)
 
     # ------------------------------------------------------------ ER and grid workloads
     if not args.no_extras and not args.no_configs:

@@ -76,10 +76,18 @@ enum {
   GCONN_LINK_LP = 7,      /* label propagation                                     */
   GCONN_LINK_AFFOREST = 8, /* G_Afforest: Afforest's link (walk two levels, CAS a
                              root under the lower side), separate full compress   */
-  GCONN_LINK_REM_LOCK = 9 /* Union-Rem-Lock: Rem's algorithm, the root link made
+  GCONN_LINK_REM_LOCK = 9, /* Union-Rem-Lock: Rem's algorithm, the root link made
                              under a per-vertex try-lock (wave-safe: a lane that
                              gets the lock finishes and releases it in the same
                              step, so lanes of one wave never wait on each other) */
+  GCONN_LINK_JTB = 10     /* Union-JTB: randomized linking by rank (Jayanti, Tarjan
+                             and Boix-Adsera); parent and rank share one 64-bit word
+                             updated by 64-bit CAS, ties broken by a seeded random
+                             key; finds are FIND_NAIVE (FindSimple) or
+                             FIND_TWO_TRY_SPLIT.  Roots are not component minima,
+                             so labels come from a separate minimum reduction.
+                             Sampling: none or k-out; the workspace holds the words
+                             (8 bytes per vertex).  Not in batched or served calls. */
 };
 
 /* On-the-fly compression inside Find (Appendix A.2, find options). */
@@ -87,7 +95,9 @@ enum {
   GCONN_FIND_NAIVE = 0,    /* no compression                                 */
   GCONN_FIND_SPLIT = 1,    /* path splitting with CAS (AtomicSplit)          */
   GCONN_FIND_HALVE = 2,    /* path halving with CAS (AtomicHalve)            */
-  GCONN_FIND_COMPRESS = 3  /* full path compression (not for Union-Rem-CAS)  */
+  GCONN_FIND_COMPRESS = 3, /* full path compression (not for Union-Rem-CAS)  */
+  GCONN_FIND_TWO_TRY_SPLIT = 4 /* Union-JTB only: two splitting CAS tries at each
+                                  vertex of the walk before moving on       */
 };
 
 /* Splice rule of Union-Rem-CAS at a non-root (Appendix A.2, splice options). */
@@ -218,7 +228,9 @@ gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t*
  * caller-owned, must outlive the handle).  If `initial` is non-NULL its graph
  * (n <= n_max) is connected first with gconn_cc's pipeline.  Batches are
  * totally ordered on the handle's stream: a query batch sees exactly the
- * inserts enqueued before it.  A handle is not thread-safe. */
+ * inserts enqueued before it.  A handle is not thread-safe.  With
+ * GCONN_LINK_JTB the forest lives in the workspace as 64-bit (rank, parent)
+ * words and parent_buf is scratch for gconn_inc_labels. */
 typedef struct gconn_inc gconn_inc;
 
 gconn_status gconn_inc_workspace_size(uint32_t n_max, const gconn_graph* initial,

@@ -30,16 +30,24 @@ gconn_status hip_fail(hipError_t e, const char* what) {
 bool is_union_find(int link) {
   return link == GCONN_LINK_ASYNC || link == GCONN_LINK_HOOKS || link == GCONN_LINK_EARLY ||
          link == GCONN_LINK_REM_CAS || link == GCONN_LINK_ECL || link == GCONN_LINK_AFFOREST ||
-         link == GCONN_LINK_REM_LOCK;
+         link == GCONN_LINK_REM_LOCK || link == GCONN_LINK_JTB;
 }
 
 gconn_status check_options(const gconn_options& o) {
   if (o.sample < GCONN_SAMPLE_NONE || o.sample > GCONN_SAMPLE_BFS)
     return fail(GCONN_EINVAL, "options.sample out of range");
-  if (o.link < GCONN_LINK_ASYNC || o.link > GCONN_LINK_REM_LOCK)
+  if (o.link < GCONN_LINK_ASYNC || o.link > GCONN_LINK_JTB)
     return fail(GCONN_EINVAL, "options.link out of range");
-  if (o.find < GCONN_FIND_NAIVE || o.find > GCONN_FIND_COMPRESS)
+  if (o.find < GCONN_FIND_NAIVE || o.find > GCONN_FIND_TWO_TRY_SPLIT)
     return fail(GCONN_EINVAL, "options.find out of range");
+  if (o.link == GCONN_LINK_JTB) {
+    if (o.find != GCONN_FIND_NAIVE && o.find != GCONN_FIND_TWO_TRY_SPLIT)
+      return fail(GCONN_EUNSUPPORTED, "Union-JTB finds are FindSimple (NAIVE) or TwoTrySplit");
+    if (o.sample != GCONN_SAMPLE_NONE && o.sample != GCONN_SAMPLE_KOUT)
+      return fail(GCONN_EUNSUPPORTED, "Union-JTB samples with k-out or not at all");
+  } else if (o.find == GCONN_FIND_TWO_TRY_SPLIT) {
+    return fail(GCONN_EUNSUPPORTED, "FIND_TWO_TRY_SPLIT belongs to Union-JTB");
+  }
   if (o.splice < GCONN_SPLICE_SPLIT_ONE || o.splice > GCONN_SPLICE_ATOMIC)
     return fail(GCONN_EINVAL, "options.splice out of range");
   if (o.lt_variant < 0 || o.lt_variant >= GCONN_LT_COUNT)
@@ -144,6 +152,7 @@ struct gconn_inc {
   uint32_t n_max;
   uint32_t* P;
   uint32_t* H;
+  uint64_t* W;  // Union-JTB words (in the workspace), else NULL
   uint8_t* ws;
   size_t ws_bytes;
   gconn_options opt;
@@ -287,6 +296,7 @@ gconn_status gconn_inc_workspace_size(uint32_t n_max, const gconn_graph* initial
   GCONN_TRY(resolve_options(opt, &o));
   size_t total = align_up(sizeof(Ctrl), 256);
   if (needs_claims(o.link)) total += align_up(4ull * n_max + 1, 256);
+  if (o.link == GCONN_LINK_JTB) total += align_up(8ull * n_max + 1, 256);
   if (initial) total += plan_workspace(*initial, o, false, true).total;
   *bytes = total;
   return GCONN_OK;
@@ -316,23 +326,36 @@ gconn_status gconn_inc_create(uint32_t n_max, uint32_t* parent_buf, const gconn_
   uint8_t* ws = static_cast<uint8_t*>(workspace);
   size_t at = align_up(sizeof(Ctrl), 256);
   uint32_t* H = nullptr;
+  uint64_t* W = nullptr;
   if (needs_claims(o.link)) {
     H = reinterpret_cast<uint32_t*>(ws + at);
     at += align_up(4ull * n_max + 1, 256);
   }
-  GCONN_TRY(launch_iota(parent_buf, n_max, s));
+  if (o.link == GCONN_LINK_JTB) {
+    W = reinterpret_cast<uint64_t*>(ws + at);
+    at += align_up(8ull * n_max + 1, 256);
+    GCONN_TRY(launch_jtb_init(W, n_max, s));
+  } else {
+    GCONN_TRY(launch_iota(parent_buf, n_max, s));
+  }
   if (H) GCONN_TRY(launch_fill(H, 0xFFFFFFFFu, n_max, s));
   if (initial && initial->n > 0) {
     gconn_options io = o;
     if (initial->format == GCONN_COO) io.sample = GCONN_SAMPLE_NONE;
     const WsLayout L = plan_workspace(*initial, io, false, true);
-    GCONN_TRY(run_static(*initial, parent_buf, nullptr, nullptr, true, ws + at, L, io, nullptr, s));
+    if (W)
+      GCONN_TRY(run_static_jtb(*initial, nullptr, nullptr, nullptr, false, ws + at, L, io, nullptr,
+                               s, W));
+    else
+      GCONN_TRY(
+          run_static(*initial, parent_buf, nullptr, nullptr, true, ws + at, L, io, nullptr, s));
   }
   gconn_inc* h = new (std::nothrow) gconn_inc;
   if (!h) return fail(GCONN_EINVAL, "host allocation of the handle failed");
   h->n_max = n_max;
   h->P = parent_buf;
   h->H = H;
+  h->W = W;
   h->ws = ws;
   h->ws_bytes = workspace_bytes;
   h->opt = o;
@@ -352,6 +375,7 @@ gconn_status gconn_inc_insert_batch(gconn_inc* h, const uint32_t* src, const uin
   GCONN_TRY(check_device_ptr(dst, "dst"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (h->opt.validate) GCONN_TRY(validate_ids(h, src, dst, k, s));
+  if (h->W) return launch_jtb_insert(h->opt, h->W, src, dst, k, s);
   return launch_insert(h->opt, h->P, h->H, src, dst, k, s);
 }
 
@@ -365,6 +389,7 @@ gconn_status gconn_inc_query_batch(gconn_inc* h, const uint32_t* a, const uint32
   GCONN_TRY(check_device_ptr(out, "out"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (h->opt.validate) GCONN_TRY(validate_ids(h, a, b, q, s));
+  if (h->W) return launch_jtb_query(h->opt, h->W, nullptr, a, b, q, out, s);
   return launch_query(h->opt, h->P, a, b, q, out, s);
 }
 
@@ -382,6 +407,7 @@ gconn_status gconn_inc_mixed_batch(gconn_inc* h, const uint8_t* kind, const uint
     GCONN_TRY(validate_ids(h, a, b, count, s));
     GCONN_TRY(validate_kinds(kind, count, reinterpret_cast<Ctrl*>(h->ws), s));
   }
+  if (h->W) return launch_jtb_mixed(h->opt, h->W, kind, a, b, count, out, s);
   return launch_mixed(h->opt, h->P, h->H, kind, a, b, count, out, s);
 }
 
@@ -390,6 +416,8 @@ gconn_status gconn_inc_labels(gconn_inc* h, uint32_t* labels_out, void* stream) 
   if (!h) return fail(GCONN_EINVAL, "handle is NULL");
   if (h->n_max == 0) return GCONN_OK;
   GCONN_TRY(check_device_ptr(labels_out, "labels_out"));
+  if (h->W)
+    return launch_jtb_labels(h->W, h->n_max, labels_out, h->P, static_cast<hipStream_t>(stream));
   return launch_finalize(h->P, h->n_max, labels_out, static_cast<hipStream_t>(stream));
 }
 

@@ -66,6 +66,8 @@ struct WsLayout {
   size_t fr_bits0 = 0, fr_bits1 = 0;  // BFS frontier bitmaps
   size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
   size_t resid = 0;   // k-out pre-link: residual sampled edges (uint2[n])
+  size_t words = 0;   // Union-JTB (rank, parent) words (uint64[n])
+  size_t roots = 0;   // Union-JTB flat roots, then component minima (uint32[n])
   uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;
@@ -118,6 +120,30 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
 gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_t* fv,
                         bool finalize, uint8_t* ws, const WsLayout& L, const gconn_options& o,
                         gconn_stats* stats, hipStream_t s);
+
+// Synchronous check of a graph's offsets and ids; uses ctrl->err.
+gconn_status validate_graph(const gconn_graph& g, Ctrl* ctrl, uint32_t block, hipStream_t s);
+
+// Union-JTB (gconn_jtb.hip): the same pipeline over 64-bit (rank, parent)
+// words.  words: the word array to use (nullable: the workspace's own); P
+// receives canonical labels when finalize is set.
+WsLayout plan_workspace_jtb(const gconn_graph& g, const gconn_options& o, bool forest, bool labels);
+gconn_status run_static_jtb(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_t* fv,
+                            bool finalize, uint8_t* ws, const WsLayout& L, const gconn_options& o,
+                            gconn_stats* stats, hipStream_t s, uint64_t* words);
+gconn_status launch_jtb_init(uint64_t* W, uint32_t n, hipStream_t s);
+gconn_status launch_jtb_insert(const gconn_options& o, uint64_t* W, const uint32_t* src,
+                               const uint32_t* dst, uint64_t k, hipStream_t s);
+// kind: nullable (plain query batch); else a mixed batch's queries only.
+gconn_status launch_jtb_query(const gconn_options& o, uint64_t* W, const uint8_t* kind,
+                              const uint32_t* a, const uint32_t* b, uint64_t q, uint8_t* out,
+                              hipStream_t s);
+gconn_status launch_jtb_mixed(const gconn_options& o, uint64_t* W, const uint8_t* kind,
+                              const uint32_t* a, const uint32_t* b, uint64_t count, uint8_t* out,
+                              hipStream_t s);
+// Canonical labels (component minima) from the words; scratch: n entries.
+gconn_status launch_jtb_labels(const uint64_t* W, uint32_t n, uint32_t* labels, uint32_t* scratch,
+                               hipStream_t s);
 
 // Incremental helpers implemented next to the static kernels.
 gconn_status launch_iota(uint32_t* P, uint32_t n, hipStream_t s);

@@ -281,7 +281,8 @@ gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* paren
   if (!cfg || !out) return fail(GCONN_EINVAL, "cfg and out are required");
   *out = nullptr;
   GCONN_TRY(check_options(cfg->options));
-  if (!is_union_find(cfg->options.link) || needs_claims(cfg->options.link))
+  if (!is_union_find(cfg->options.link) || needs_claims(cfg->options.link) ||
+      cfg->options.link == GCONN_LINK_JTB)
     return fail(GCONN_EUNSUPPORTED,
                 "the server runs Union-Async, Union-Early, Union-Rem-CAS, ECL-CC's rule or "
                 "G_Afforest's link");

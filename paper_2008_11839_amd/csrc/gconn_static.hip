@@ -1936,6 +1936,7 @@ gconn_status validate_pairs(const uint32_t* a, const uint32_t* b, uint64_t k, ui
 }
 
 WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool forest, bool labels) {
+  if (o.link == GCONN_LINK_JTB) return plan_workspace_jtb(g, o, forest, labels);
   WsLayout L;
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -1980,9 +1981,31 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
   return L;
 }
 
+gconn_status validate_graph(const gconn_graph& g, Ctrl* ctrl, uint32_t block, hipStream_t s) {
+  const uint32_t n = g.n;
+  if (g.format == GCONN_CSR) {
+    if (g.offsets_64)
+      k_validate_csr<uint64_t><<<grid_for(std::max<uint64_t>(g.m, n), block), block, 0, s>>>(
+          static_cast<const uint64_t*>(g.offsets), g.nbrs, n, g.m, ctrl);
+    else
+      k_validate_csr<uint32_t><<<grid_for(std::max<uint64_t>(g.m, n), block), block, 0, s>>>(
+          static_cast<const uint32_t*>(g.offsets), g.nbrs, n, g.m, ctrl);
+  } else {
+    k_validate_ids<<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m, n, ctrl);
+  }
+  GCONN_LAUNCHED("k_validate");
+  uint32_t err = 0;
+  GCONN_HIP(hipMemcpyAsync(&err, &ctrl->err, sizeof(err), hipMemcpyDeviceToHost, s));
+  GCONN_HIP(hipStreamSynchronize(s));
+  if (err) return fail(GCONN_EINVAL, "graph validation failed (offsets or vertex id out of range)");
+  return GCONN_OK;
+}
+
 gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_t* fv,
                         bool finalize, uint8_t* ws, const WsLayout& L, const gconn_options& o,
                         gconn_stats* stats, hipStream_t s) {
+  if (o.link == GCONN_LINK_JTB)
+    return run_static_jtb(g, P, fu, fv, finalize, ws, L, o, stats, s, nullptr);
   Run run(g, P, fu, fv, ws, L, o, stats != nullptr, s);
   const uint32_t n = g.n;
   const uint32_t block = run.block;
@@ -1998,23 +2021,7 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
 
   const bool csr = g.format == GCONN_CSR;
   const bool o64 = g.offsets_64 != 0;
-  if (o.validate && (g.m > 0 || csr)) {
-    if (csr) {
-      if (o64)
-        k_validate_csr<uint64_t><<<grid_for(std::max<uint64_t>(g.m, n), block), block, 0, s>>>(
-            static_cast<const uint64_t*>(g.offsets), g.nbrs, n, g.m, run.ctrl);
-      else
-        k_validate_csr<uint32_t><<<grid_for(std::max<uint64_t>(g.m, n), block), block, 0, s>>>(
-            static_cast<const uint32_t*>(g.offsets), g.nbrs, n, g.m, run.ctrl);
-    } else {
-      k_validate_ids<<<grid_for(g.m, block), block, 0, s>>>(g.nbrs, g.dst, g.m, n, run.ctrl);
-    }
-    GCONN_LAUNCHED("k_validate");
-    uint32_t err = 0;
-    GCONN_HIP(hipMemcpyAsync(&err, &run.ctrl->err, sizeof(err), hipMemcpyDeviceToHost, s));
-    GCONN_HIP(hipStreamSynchronize(s));
-    if (err) return fail(GCONN_EINVAL, "graph validation failed (offsets or vertex id out of range)");
-  }
+  if (o.validate && (g.m > 0 || csr)) GCONN_TRY(validate_graph(g, run.ctrl, block, s));
 
   const bool iterative =
       o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;

@@ -20,8 +20,8 @@ EMPTY = 0xFFFFFFFF
 
 SAMPLE = {"none": 0, "kout": 1, "hb": 2, "bfs": 3}
 LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt": 6, "lp": 7,
-        "afforest": 8, "rem_lock": 9}
-FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3}
+        "afforest": 8, "rem_lock": 9, "jtb": 10}
+FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3, "two_try_split": 4}
 SPLICE = {"split_one": 0, "halve_one": 1, "splice_atomic": 2}
 SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3, "twopass": 4}
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",

@@ -6,8 +6,10 @@
 // edges.bin: uint32 pairs; rule: 0-3 Async (naive/split/halve/compress),
 // 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one),
 // 18-20 Rem-CAS with Rem's splice (naive/split/halve), 21 G_Afforest's link,
-// 22-25 Rem-Lock (naive/split_one, split/split_one, halve/halve_one, split/splice).
-// Writes labels (root of every vertex, uint32) and prints the hook count.
+// 22-25 Rem-Lock (naive/split_one, split/split_one, halve/halve_one, split/splice),
+// 26-27 Union-JTB (FindSimple, FindTwoTrySplit) on 64-bit (rank, parent) words.
+// Writes labels (the minimum vertex of every vertex's tree, uint32) and prints
+// the hook count.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -16,6 +18,7 @@
 #include <thread>
 #include <vector>
 
+#include "../../paper_2008_11839_amd/csrc/gconn_jtb.hpp"
 #include "../../paper_2008_11839_amd/csrc/gconn_rules.hpp"
 
 using namespace gconn;
@@ -32,6 +35,51 @@ void run(const std::vector<uint32_t>& e, LinkCtx c, int threads) {
   for (auto& th : ts) th.join();
 }
 
+template <int F>
+void run_jtb(const std::vector<uint32_t>& e, JtbCtx c, int threads) {
+  const size_t m = e.size() / 2;
+  std::vector<std::thread> ts;
+  for (int t = 0; t < threads; ++t)
+    ts.emplace_back([&, t] {
+      for (size_t i = t; i < m; i += threads) jtb_unite<F>(c, e[2 * i], e[2 * i + 1]);
+    });
+  for (auto& th : ts) th.join();
+}
+
+// Union-JTB: every parent must lie above its child in the (rank, key) order
+// and hold a rank no lower; labels are the minimum vertex of each tree.
+int jtb_main(const std::vector<uint32_t>& e, uint32_t n, int rule, int threads, const char* out) {
+  std::vector<uint64_t> W(n);
+  for (uint32_t v = 0; v < n; ++v) W[v] = jtb_word(v, 0);
+  unsigned long long hooks = 0;
+  const uint32_t salt = 0x9e3779b9u;
+  JtbCtx c{W.data(), nullptr, nullptr, &hooks, salt};
+  if (rule == 26) run_jtb<kJtbFindSimple>(e, c, threads);
+  else run_jtb<kJtbFindTwoTrySplit>(e, c, threads);
+  std::vector<uint32_t> root(n), lab(n);
+  for (uint32_t v = 0; v < n; ++v) {
+    uint32_t r = v;
+    for (;;) {
+      const uint32_t p = jtb_parent(W[r]);
+      if (p == r) break;
+      if (jtb_rank(W[p]) < jtb_rank(W[r])) return 6;
+      if (!jtb_below(W[r], r, W[p], p, salt)) return 6;
+      r = p;
+    }
+    root[v] = r;
+  }
+  for (uint32_t v = 0; v < n; ++v) lab[v] = kEmpty;
+  for (uint32_t v = 0; v < n; ++v)
+    if (v < lab[root[v]]) lab[root[v]] = v;
+  for (uint32_t v = 0; v < n; ++v) lab[v] = lab[root[v]];
+  FILE* o = fopen(out, "wb");
+  if (!o) return 7;
+  fwrite(lab.data(), 4, n, o);
+  fclose(o);
+  printf("%llu\n", hooks);
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc != 6 && argc != 7) return 2;
   FILE* f = fopen(argv[1], "rb");
@@ -45,6 +93,7 @@ int main(int argc, char** argv) {
   const int rule = atoi(argv[3]), threads = atoi(argv[4]);
   for (uint32_t x : e)
     if (x >= n) return 4;
+  if (rule == 26 || rule == 27) return jtb_main(e, n, rule, threads, argv[5]);
   std::vector<uint32_t> P(n), H(n, kEmpty);
   for (uint32_t v = 0; v < n; ++v) P[v] = v;
   unsigned long long hooks = 0;

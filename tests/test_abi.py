@@ -127,3 +127,30 @@ def test_compute_without_a_gpu_fails_loudly():
     h = ctypes.c_void_p()
     st = gconn.lib().gconn_inc_create(10, None, None, None, 0, None, None, ctypes.byref(h))
     assert st in (-4, -7)
+
+
+def test_jtb_options_and_workspace():
+    g = _graph(1000, 8000)
+    b = ctypes.c_size_t()
+
+    def status(**kw):
+        o = gconn.Options(**kw).to_c()
+        return gconn.lib().gconn_workspace_size(ctypes.byref(g), ctypes.byref(o), 0, 1,
+                                                ctypes.byref(b))
+    assert status(link="jtb", find="naive") == 0
+    assert status(link="jtb", find="two_try_split", sample="kout") == 0
+    assert status(link="jtb", find="two_try_split", sample="none") == 0
+    for find in ("split", "halve", "compress"):
+        assert status(link="jtb", find=find) == -7
+    for sample in ("hb", "bfs"):
+        assert status(link="jtb", find="naive", sample=sample) == -7
+    assert status(link="async", find="two_try_split") == -7
+    # the words (8 bytes per vertex) and the root array (4) are in the plan
+    n, m = 1 << 20, 1 << 22
+    st, base = _ws(_graph(n, m), link="async")
+    st2, jtb = _ws(_graph(n, m), link="jtb", find="naive")
+    assert st == 0 and st2 == 0 and jtb - base >= 12 * n
+    # the incremental handle keeps the words in its workspace
+    o = gconn.Options(link="jtb", find="naive", sample="none").to_c()
+    assert gconn.lib().gconn_inc_workspace_size(n, None, ctypes.byref(o), ctypes.byref(b)) == 0
+    assert b.value >= 8 * n

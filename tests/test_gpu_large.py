@@ -29,7 +29,9 @@ CONFIGS = [dict(sample=s, link=l, find=f, splice=sp)
                                ("none", "rem_cas", "split", "split_one"),
                                ("none", "async", "halve", "split_one"),
                                ("hb", "async", "split", "split_one"),
-                               ("bfs", "rem_cas", "split", "split_one")]]
+                               ("bfs", "rem_cas", "split", "split_one"),
+                               ("kout", "jtb", "two_try_split", "split_one"),
+                               ("none", "jtb", "naive", "split_one")]]
 
 
 def say(*a):
@@ -53,7 +55,7 @@ def test_rmat22_labels_match_oracle(rmat22, ac, prelink):
     C, dg, want = rmat22
     c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
     for cfg in CONFIGS:
-        if prelink and cfg["sample"] != "kout":
+        if prelink and (cfg["sample"] != "kout" or cfg["link"] == "jtb"):
             continue
         o = G.Options(atomic_compress=ac, kout_prelink=prelink is True,
                       kout_local=prelink == "local",
@@ -95,7 +97,8 @@ def test_rmat22_incremental(rmat22, ac):
     keep = src < dst
     src, dst = src[keep], dst[keep]
     graphgen.shuffle_edges(src, dst, 3)
-    for link, find in (("async", "split"), ("rem_cas", "split"), ("early", "halve")):
+    for link, find in (("async", "split"), ("rem_cas", "split"), ("early", "halve"),
+                       ("jtb", "two_try_split")):
         say(f"[rmat22 inc] link={link} find={find} atomic_compress={ac}")
         inc = G.Incremental(C.n, options=G.Options(sample="none", link=link, find=find,
                                                    atomic_compress=ac))

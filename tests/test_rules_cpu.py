@@ -1,7 +1,8 @@
-"""The library's union-find rules (gconn_rules.hpp) compiled for the host and
-run concurrently from many threads: labels equal the oracle's, every parent
-points to a smaller id, and exactly n - c links succeed, with compression
-writes as CAS and as relaxed stores."""
+"""The library's union-find rules (gconn_rules.hpp, gconn_jtb.hpp) compiled
+for the host and run concurrently from many threads: labels equal the
+oracle's, every parent points to a smaller id (Union-JTB: to a vertex above it
+in the rank order), and exactly n - c links succeed, with compression writes
+as CAS and as relaxed stores."""
 from __future__ import annotations
 
 import os
@@ -16,7 +17,7 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "native", "rules_stress.hip")
 BIN = os.path.join(ROOT, "_build", "tests", "rules_stress")
-RULES = list(range(26))
+RULES = list(range(28))
 
 
 @pytest.fixture(scope="module")
