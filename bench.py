@@ -303,6 +303,19 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
                 "insert_latency_ms_p50": round(percentile(i, 50), 3),
                 "insert_latency_ms_p99": round(percentile(i, 99), 3)}
 
+    # the link the host-fed mode is bound by: pinned host -> device, 1 GiB
+    import torch
+    hbuf = torch.empty(1 << 28, dtype=torch.int32, pin_memory=True)
+    dbuf = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    dbuf.copy_(hbuf, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dbuf.copy_(hbuf, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_gbs = 3 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+    del hbuf, dbuf
+
     wall, lat, recs = run(None)
     sat_rate = len(host) / wall
     out = {"saturated": {"updates_per_s": round(updates / wall, 1),
@@ -315,6 +328,8 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
                               "latency_ms_p50": round(percentile(lat, 50), 3),
                               "latency_ms_p99": round(percentile(lat, 99), 3), **by_kind(lat)}
     out["updates"], out["queries"] = updates, queries
+    out["h2d_pinned_gbs"] = round(h2d_gbs, 2)
+    out["h2d_bound_updates_per_s"] = round(h2d_gbs * 1e9 / 8, 1)  # 8 bytes per update
     return out
 
 

@@ -3,18 +3,18 @@
 // device work is the incremental insert / query kernels of gconn_static.hip.
 //
 // One worker thread owns every HIP call after creation.  Its loop:
-//   1. admit pending requests in submission order while the device arena and
-//      the pinned staging area have room (first-fit allocator, 256-byte
-//      granules); a request that does not fit stops admission until earlier
-//      requests complete and free space;
+//   1. admit the next pending request, in submission order, when the device
+//      arena and the pinned staging area have room for it (first-fit
+//      allocator, 256-byte granules); a request that does not fit stops
+//      admission until earlier requests complete and free space;
 //   2. on admission: copy the request's host data into pinned staging, pick the
 //      next stream round-robin; if its kind differs from the current epoch's,
 //      open a new epoch by recording one fence event on every stream; make the
 //      stream wait on the current epoch's fences; enqueue H2D copy, kernel,
 //      (queries) D2H of the answers, and a completion event;
-//   3. poll completion events; for finished queries copy the answers from
-//      staging into the caller's buffer; free the arena space; publish the
-//      request record and wake waiters.
+//   3. poll completion events after every admission; for finished queries
+//      copy the answers from staging into the caller's buffer; free the arena
+//      space; publish the request record and wake waiters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,51 +223,60 @@ struct gconn_server {
     cv_done.notify_all();
   }
 
+  // Publish every request whose completion event has fired.
+  bool sweep_completions() {
+    bool progressed = false;
+    for (size_t i = 0; i < inflight.size();) {
+      const hipError_t q = hipEventQuery(inflight[i]->done);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      const gconn_status st = q == hipSuccess ? GCONN_OK : hip_fail(q, "request");
+      finish_request(inflight[i], st);
+      inflight[i] = std::move(inflight.back());
+      inflight.pop_back();
+      progressed = true;
+    }
+    return progressed;
+  }
+
   void run() {
     (void)hipSetDevice(device);
     for (;;) {
-      // 1. admission, in submission order
-      for (;;) {
-        std::unique_ptr<Request> r;
-        {
-          std::lock_guard<std::mutex> lock(mu);
-          if (pending.empty()) break;
-          uint64_t at = 0;
-          if (!space.alloc(pending.front()->bytes, &at)) break;  // wait for space
+      // 1. admit at most one request, in submission order.  Completions are
+      // swept after every admission: a steady arrival stream can keep the
+      // pending queue non-empty for a long time, and finished requests must
+      // not wait for it to drain.
+      bool admitted = false;
+      std::unique_ptr<Request> r;
+      {
+        std::lock_guard<std::mutex> lock(mu);
+        uint64_t at = 0;
+        if (!pending.empty() && space.alloc(pending.front()->bytes, &at)) {
           r = std::move(pending.front());
           pending.pop_front();
           r->at = at;
         }
+      }
+      if (r) {
+        admitted = true;
         r->stream = rr;
         rr = (rr + 1) % (int)streams.size();
         r->info.admit_us = now_us();
         const gconn_status st = launch(*r);
-        if (st != GCONN_OK) {
-          finish_request(r, st);
-          continue;
-        }
-        inflight.push_back(std::move(r));
+        if (st != GCONN_OK) finish_request(r, st);
+        else inflight.push_back(std::move(r));
       }
       // 2. completions
-      bool progressed = false;
-      for (size_t i = 0; i < inflight.size();) {
-        const hipError_t q = hipEventQuery(inflight[i]->done);
-        if (q == hipErrorNotReady) {
-          ++i;
-          continue;
-        }
-        const gconn_status st = q == hipSuccess ? GCONN_OK : hip_fail(q, "request");
-        finish_request(inflight[i], st);
-        inflight[i] = std::move(inflight.back());
-        inflight.pop_back();
-        progressed = true;
-      }
+      const bool progressed = sweep_completions() || admitted;
       // 3. sleep when idle
       std::unique_lock<std::mutex> lock(mu);
       if (stop && pending.empty() && inflight.empty()) break;
-      if (!progressed && inflight.empty() && pending.empty())
+      if (progressed) continue;
+      if (inflight.empty() && pending.empty())
         cv_work.wait_for(lock, std::chrono::milliseconds(5));
-      else if (!progressed)
+      else
         cv_work.wait_for(lock, std::chrono::microseconds(20));
     }
   }
