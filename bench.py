@@ -428,6 +428,8 @@ def other_configs_bench(G, args) -> dict:
             "grid3d_256_p0.6": (lambda: graphgen.grid3d(256, 256, 256, 0.6, args.seed),
                                 f"grid3d_256_p06_s{args.seed}")}
     cfgs = [dict(sample="kout", link="rem_cas", find="split"),
+            dict(sample="kout", link="rem_cas", find="split", schedule="twopass"),
+            dict(sample="kout", link="rem_cas", find="split", kout_local=True),
             dict(sample="none", link="rem_cas", find="split"),
             dict(sample="none", link="async", find="halve"),
             dict(sample="kout", link="sv"), dict(sample="kout", link="lt", lt_variant="PRF"),
