@@ -384,7 +384,10 @@ gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* paren
                                  void* arena, gconn_server** out);
 /* Copies nothing yet: a, b (host, count entries) and out (host, count bytes,
  * queries only: 1 iff connected) must stay valid until the request is done.
- * Returns GCONN_EINVAL for a request larger than the arena.  Thread-safe. */
+ * Pageable buffers go through the server's pinned staging area; buffers that
+ * are pinned already (hipHostMalloc, torch pin_memory) are read and written
+ * by the copy engines directly, with no host copy.  Returns GCONN_EINVAL for a
+ * request larger than the arena.  Thread-safe. */
 gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, const uint32_t* b,
                                  uint64_t count, uint8_t* out, uint64_t* ticket);
 /* Blocks until the request is done or timeout_s (< 0: no limit) elapses

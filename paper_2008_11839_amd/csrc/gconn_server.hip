@@ -2,16 +2,20 @@
 // connectivity (gconn_server_* in include/gconn.h).  Host code only: the
 // device work is the incremental insert / query kernels of gconn_static.hip.
 //
-// One worker thread owns every HIP call after creation.  Its loop:
+// One worker thread owns every copy, launch, event and stream call after
+// creation (submit only asks whether the caller's buffers are pinned).  Its
+// loop:
 //   1. admit the next pending request, in submission order, when the device
 //      arena and the pinned staging area have room for it (first-fit
 //      allocator, 256-byte granules); a request that does not fit stops
 //      admission until earlier requests complete and free space;
-//   2. on admission: copy the request's host data into pinned staging, pick the
-//      next stream round-robin; if its kind differs from the current epoch's,
-//      open a new epoch by recording one fence event on every stream; make the
-//      stream wait on the current epoch's fences; enqueue H2D copy, kernel,
-//      (queries) D2H of the answers, and a completion event;
+//   2. on admission: copy the request's host data into pinned staging (unless
+//      the caller's buffers are pinned already: then the copy engines read
+//      and write them directly), pick the next stream round-robin; if its
+//      kind differs from the current epoch's, open a new epoch by recording
+//      one fence event on every stream; enqueue the H2D copies, make the
+//      stream wait on the current epoch's fences, then enqueue the kernel,
+//      (queries) the D2H of the answers, and a completion event;
 //   3. poll completion events after every admission; for finished queries
 //      copy the answers from staging into the caller's buffer; free the arena
 //      space; publish the request record and wake waiters.
@@ -36,7 +40,7 @@ namespace gconn {
 namespace {
 
 constexpr uint64_t kGranule = 256;
-constexpr uint64_t kInsertChunk = 4u << 20;  // edges per chunk of a large insert batch
+constexpr uint64_t kInsertChunk = 4u << 20;  // pairs per staged chunk of a large batch
 
 // Host copy into pinned staging, split over a few threads for large requests:
 // one thread's memcpy (~10 GB/s) would otherwise cap the host-fed rate well
@@ -103,10 +107,23 @@ struct Request {
   uint64_t count = 0;
   uint64_t bytes = 0;     // arena / staging footprint
   uint64_t at = 0;        // offset in the arena and staging area
+  bool pinned_in = false;  // a and b are pinned host memory: copied without staging
+  bool pinned_out = false; // out is pinned host memory: answers copied straight to it
   int stream = 0;
   hipEvent_t done = nullptr;
   gconn_request_info info{};
 };
+
+// Is p page-locked host memory the DMA engines can read directly (allocated
+// with hipHostMalloc, or torch's pin_memory)?  Pageable memory is not.
+bool is_pinned_host(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory: leave no error for later calls
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost;
+}
 
 uint64_t footprint(int kind, uint64_t count) {
   const uint64_t raw = kind == GCONN_REQ_INSERT ? 8 * count : 9 * count;
@@ -133,7 +150,10 @@ struct gconn_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::unique_ptr<Request>> pending;  // submitted, not admitted
-  std::vector<std::unique_ptr<Request>> inflight;
+  // Admitted requests per stream, oldest first: a stream runs its work in
+  // order, so its requests complete in this order.
+  std::vector<std::deque<std::unique_ptr<Request>>> inflight;
+  size_t inflight_count = 0;
   std::unordered_map<uint64_t, gconn_request_info> finished;
   uint64_t next_ticket = 1;
   uint64_t submitted = 0, completed = 0;
@@ -173,36 +193,41 @@ struct gconn_server {
       ++epoch;
     }
     r.info.epoch = epoch;
-    // The fences of the current epoch order this request after every earlier
-    // epoch; waiting on a fence that is older than the stream's own work is a
-    // no-op for correctness.
-    if (epoch > 1)
-      for (size_t t = 0; t < streams.size(); ++t) GCONN_HIP(hipStreamWaitEvent(s, fences[t], 0));
     uint8_t* dev = arena + r.at;
     uint8_t* host = staging + r.at;
     uint32_t* da = reinterpret_cast<uint32_t*>(dev);
     uint32_t* db = da + r.count;
-    if (r.kind == GCONN_REQ_INSERT) {
-      // Large insert batches go in chunks, so that the host copy of one chunk
-      // overlaps the transfer and the union kernel of the previous one.
-      uint32_t* H = nullptr;  // rules with a claim array are not offered by the server
-      uint32_t* ha = reinterpret_cast<uint32_t*>(host);
-      uint32_t* hb = ha + r.count;
-      for (uint64_t lo = 0; lo < r.count; lo += kInsertChunk) {
-        const uint64_t len = std::min<uint64_t>(kInsertChunk, r.count - lo);
+    // Transfers first: they touch only this request's arena range, so they
+    // need not wait for earlier epochs and overlap the kernels still running
+    // there.  Large pageable inputs are staged in chunks, so that the host
+    // copy of one chunk overlaps the transfer of the previous one; pinned
+    // inputs are read by the copy engines directly.
+    uint32_t* ha = reinterpret_cast<uint32_t*>(host);
+    uint32_t* hb = ha + r.count;
+    const uint32_t* sa = r.pinned_in ? r.a : ha;
+    const uint32_t* sb = r.pinned_in ? r.b : hb;
+    for (uint64_t lo = 0; lo < r.count; lo += kInsertChunk) {
+      const uint64_t len = std::min<uint64_t>(kInsertChunk, r.count - lo);
+      if (!r.pinned_in) {
         staged_copy(ha + lo, r.a + lo, 4 * len);
         staged_copy(hb + lo, r.b + lo, 4 * len);
-        GCONN_HIP(hipMemcpyAsync(da + lo, ha + lo, 4 * len, hipMemcpyHostToDevice, s));
-        GCONN_HIP(hipMemcpyAsync(db + lo, hb + lo, 4 * len, hipMemcpyHostToDevice, s));
-        GCONN_TRY(launch_insert(cfg.options, P, H, da + lo, db + lo, len, s));
       }
+      GCONN_HIP(hipMemcpyAsync(da + lo, sa + lo, 4 * len, hipMemcpyHostToDevice, s));
+      GCONN_HIP(hipMemcpyAsync(db + lo, sb + lo, 4 * len, hipMemcpyHostToDevice, s));
+    }
+    // The kernel waits on the fences of the current epoch, which order it
+    // after every earlier epoch's work on every stream; waiting on a fence
+    // older than the stream's own work is a no-op for correctness.
+    if (epoch > 1)
+      for (size_t t = 0; t < streams.size(); ++t) GCONN_HIP(hipStreamWaitEvent(s, fences[t], 0));
+    if (r.kind == GCONN_REQ_INSERT) {
+      uint32_t* H = nullptr;  // rules with a claim array are not offered by the server
+      GCONN_TRY(launch_insert(cfg.options, P, H, da, db, r.count, s));
     } else {
-      staged_copy(host, r.a, 4 * r.count);
-      staged_copy(host + 4 * r.count, r.b, 4 * r.count);
-      GCONN_HIP(hipMemcpyAsync(dev, host, 8 * r.count, hipMemcpyHostToDevice, s));
       uint8_t* dout = dev + 8 * r.count;
       GCONN_TRY(launch_query(cfg.options, P, da, db, r.count, dout, s));
-      GCONN_HIP(hipMemcpyAsync(host + 8 * r.count, dout, r.count, hipMemcpyDeviceToHost, s));
+      GCONN_HIP(hipMemcpyAsync(r.pinned_out ? r.out : host + 8 * r.count, dout, r.count,
+                               hipMemcpyDeviceToHost, s));
     }
     r.done = get_event();
     if (!r.done) return fail(GCONN_EDEVICE, "hipEventCreate failed");
@@ -211,7 +236,7 @@ struct gconn_server {
   }
 
   void finish_request(std::unique_ptr<Request>& r, gconn_status st) {
-    if (st == GCONN_OK && r->kind == GCONN_REQ_QUERY && r->out)
+    if (st == GCONN_OK && r->kind == GCONN_REQ_QUERY && r->out && !r->pinned_out)
       std::memcpy(r->out, staging + r->at + 8 * r->count, r->count);
     space.release(r->at, r->bytes);
     if (r->done) event_pool.push_back(r->done);
@@ -223,20 +248,20 @@ struct gconn_server {
     cv_done.notify_all();
   }
 
-  // Publish every request whose completion event has fired.
+  // Publish every request whose completion event has fired: per stream, from
+  // the oldest, up to the first that is still running.
   bool sweep_completions() {
     bool progressed = false;
-    for (size_t i = 0; i < inflight.size();) {
-      const hipError_t q = hipEventQuery(inflight[i]->done);
-      if (q == hipErrorNotReady) {
-        ++i;
-        continue;
+    for (auto& q : inflight) {
+      while (!q.empty()) {
+        const hipError_t e = hipEventQuery(q.front()->done);
+        if (e == hipErrorNotReady) break;
+        const gconn_status st = e == hipSuccess ? GCONN_OK : hip_fail(e, "request");
+        finish_request(q.front(), st);
+        q.pop_front();
+        --inflight_count;
+        progressed = true;
       }
-      const gconn_status st = q == hipSuccess ? GCONN_OK : hip_fail(q, "request");
-      finish_request(inflight[i], st);
-      inflight[i] = std::move(inflight.back());
-      inflight.pop_back();
-      progressed = true;
     }
     return progressed;
   }
@@ -266,15 +291,19 @@ struct gconn_server {
         r->info.admit_us = now_us();
         const gconn_status st = launch(*r);
         if (st != GCONN_OK) finish_request(r, st);
-        else inflight.push_back(std::move(r));
+        else {
+          const int sid = r->stream;
+          inflight[sid].push_back(std::move(r));
+          ++inflight_count;
+        }
       }
       // 2. completions
       const bool progressed = sweep_completions() || admitted;
       // 3. sleep when idle
       std::unique_lock<std::mutex> lock(mu);
-      if (stop && pending.empty() && inflight.empty()) break;
+      if (stop && pending.empty() && inflight_count == 0) break;
       if (progressed) continue;
-      if (inflight.empty() && pending.empty())
+      if (inflight_count == 0 && pending.empty())
         cv_work.wait_for(lock, std::chrono::milliseconds(5));
       else
         cv_work.wait_for(lock, std::chrono::microseconds(20));
@@ -321,6 +350,7 @@ gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* paren
     GCONN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     s->fences.push_back(e);
   }
+  s->inflight.resize(s->streams.size());
   GCONN_TRY(launch_iota(parent_buf, cfg->n_max, s->streams[0]));
   GCONN_HIP(hipStreamSynchronize(s->streams[0]));
   s->t0 = std::chrono::steady_clock::now();
@@ -348,6 +378,10 @@ gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, c
     return fail(GCONN_EINVAL, "request larger than the server arena");
   r->info.kind = kind;
   r->info.count = count;
+  if (count > 0) {
+    r->pinned_in = is_pinned_host(a) && is_pinned_host(b);
+    r->pinned_out = kind == GCONN_REQ_QUERY && is_pinned_host(out);
+  }
   {
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) return fail(GCONN_EBUSY, "server is shutting down");

@@ -487,10 +487,18 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, kind: int, a: np.ndarray, b: np.ndarray) -> int:
+    def submit(self, kind: int, a: np.ndarray, b: np.ndarray,
+               out: np.ndarray | None = None) -> int:
+        """a, b (and out, queries) stay referenced until wait(); arrays over
+        pinned host memory (e.g. torch pin_memory tensors' .numpy()) are
+        transferred without the server's staging copy."""
         a = np.ascontiguousarray(a, dtype=np.uint32)
         b = np.ascontiguousarray(b, dtype=np.uint32)
-        out = np.zeros(len(a), np.uint8) if kind == QUERY else None
+        if kind == QUERY and out is None:
+            out = np.zeros(len(a), np.uint8)
+        if out is not None and (out.dtype != np.uint8 or not out.flags.c_contiguous
+                                or len(out) < len(a)):
+            raise ValueError("out must be a contiguous uint8 array of len(a) entries")
         t = ctypes.c_uint64()
         _check(lib().gconn_server_submit(self._h, kind, a.ctypes.data if len(a) else None,
                                          b.ctypes.data if len(b) else None, len(a),

@@ -149,3 +149,45 @@ def test_server_rejects_oversized_and_bad_requests(gpu_available):
     srv.close()
     with pytest.raises(G.GconnError):
         G.Server(100, options=G.Options(sample="none", link="sv"))
+
+
+def test_server_pinned_buffers_skip_staging(gpu_available):
+    """Requests whose buffers are pinned host memory (read and written by the
+    copy engines directly) mixed with pageable ones: every answer equals the
+    oracle's, run alone and overlapped."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+
+    def pinned(x, dtype):
+        t = torch.empty(max(len(x), 1), dtype=dtype, pin_memory=True)
+        arr = t.numpy()[: len(x)]
+        arr[:] = x.view(arr.dtype) if x.dtype != arr.dtype else x
+        return t, arr
+
+    n = 20000
+    reqs = _stream(n, 13)
+    want = _oracle_answers(n, reqs)
+    keep, staged = [], []
+    for i, (kind, a, b) in enumerate(reqs):
+        if i % 3 == 2:  # every third request stays pageable
+            staged.append((kind, a, b, None))
+            continue
+        ta, pa = pinned(a, torch.int32)
+        tb, pb = pinned(b, torch.int32)
+        out = None
+        if kind == 1:
+            to, out = pinned(np.zeros(len(a), np.uint8), torch.uint8)
+            keep.append(to)
+        keep += [ta, tb]
+        staged.append((kind, pa.view(np.uint32), pb.view(np.uint32), out))
+    for streams, arena in ((1, 1 << 20), (4, 600 << 10)):
+        say(f"[server-pinned] streams={streams} arena={arena}")
+        srv = G.Server(n, streams=streams, arena_bytes=arena,
+                       options=G.Options(sample="none", link="async", find="split"))
+        tickets = [srv.submit(k, a, b, out) for k, a, b, out in staged]
+        for i, t in enumerate(tickets):
+            rec, out = srv.wait(t, timeout=60.0)
+            assert rec["status"] == 0
+            if reqs[i][0] == 1:
+                assert np.array_equal(out, want[i]), (streams, i)
+        srv.close()
