@@ -31,7 +31,10 @@ CONFIGS = [dict(sample="kout", link="rem_cas", find="split", splice="split_one")
            dict(sample="hb", link="async", find="split"),
            dict(sample="none", link="rem_cas", find="split"),
            dict(sample="kout", link="sv"),
-           dict(sample="kout", link="lt", lt_variant="PRF")]
+           dict(sample="kout", link="lt", lt_variant="PRF"),
+           dict(sample="kout", link="jtb", find="two_try_split"),
+           dict(sample="kout", link="afforest"),
+           dict(sample="kout", link="hooks", find="split")]
 
 
 def say(*a):
@@ -64,7 +67,8 @@ def test_full_size_labels_and_sampling_match_golden(gpu_available, name):
         if cfg["sample"] in ("kout", "hb") and cfg["link"] not in ("sv", "lt"):
             g = gold[cfg["sample"]]
             assert st["sampled_edges"] == g["sampled_edges"], (name, cfg)
-            assert st["lmax"] == g["lmax"], (name, cfg)
+            if cfg["link"] != "jtb":  # JTB's L_max is its tree's root, not the minimum
+                assert st["lmax"] == g["lmax"], (name, cfg)
             assert st["active_vertices"] == g["active_vertices"], (name, cfg)
             assert st["finish_edges"] == g["active_edges"], (name, cfg)
         del ws
