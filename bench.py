@@ -102,6 +102,54 @@ def jtb_bytes(n: int, st: dict) -> int:
     return base
 
 
+def seeds_bench(G, args, opts, seed1_value: float) -> dict:
+    """The headline measurement on the other seeds of the same generator
+    (RMAT scale and edge factor unchanged), each checked against the oracle's
+    stored labels; mean and range over all five seeds."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    dev = torch.device("cuda", 0)
+    n = 1 << args.scale
+    per_seed = {str(args.seed): round(seed1_value, 2)}
+    runs = []
+    for sd in (2, 3, 4, 5):
+        if sd == args.seed:
+            continue
+        src, dst = graphgen.rmat_edges(args.scale, args.edge_factor * n, sd)
+        C = graphgen.csr_from_edges(n, src, dst, True,
+                                    f"rmat{args.scale}_ef{args.edge_factor}_s{sd}")
+        del src, dst
+        dg = G.csr(C.offsets, C.nbrs, n)
+        lab = torch.empty(n, dtype=torch.int32, device=dev)
+        ws = G.alloc_workspace(G.workspace_size(dg, opts))
+        _, st = G.cc(dg, labels=lab, options=opts, workspace=ws, stats=True)
+        gold = golden(C.name)
+        ok = labels_sha(G.to_u32(lab)) == gold["labels_sha256"] if gold else None
+        for _ in range(args.warmup):
+            G.cc(dg, labels=lab, options=opts, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            G.cc(dg, labels=lab, options=opts, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        step_bytes = sum(algorithmic_bytes(n, C.m, st, opts.lmax_samples).values())
+        run = {"seed": sd, "m_directed": C.m, "ms_per_step": round(ms, 5),
+               "gedges_per_s": round(C.m / (ms * 1e-3) / 1e9, 2),
+               "step_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "labels_match_oracle_golden": ok}
+        runs.append(run)
+        per_seed[str(sd)] = run["gedges_per_s"]
+        log(f"seed {run}")
+        del dg, lab, ws, C
+    vals = list(per_seed.values())
+    return {"runs": runs, "gedges_per_s_by_seed": per_seed,
+            "gedges_per_s_mean": round(float(np.mean(vals)), 2),
+            "gedges_per_s_min": min(vals), "gedges_per_s_max": max(vals)}
+
+
 def finish_rules_bench(G, args, dg, n: int, m: int, gold_sha) -> dict:
     """The union-find design space on the headline graph: each finish rule
     with k-out sampling and without, timed per call (labels checked against
@@ -573,6 +621,8 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-seeds", action="store_true",
+                    help="skip the headline graph's other generator seeds (2..5)")
     ap.add_argument("--no-rules", action="store_true",
                     help="skip the union-find design-space sweep on the headline graph")
     ap.add_argument("--no-configs", action="store_true", help="skip the ER and grid workloads")
@@ -783,6 +833,10 @@ def main() -> int:
                                      "forest_edges": filled, "n_minus_c": n - comps}
         log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")
         del fu, fv, ws_f
+
+    # ------------------------------------------------------------ the other seeds
+    if not args.no_extras and not args.no_seeds:
+        result["seeds"] = seeds_bench(G, args, opts, value)
 
     # ------------------------------------------------------------ union-find design space
     if not args.no_extras and not args.no_rules:

@@ -86,8 +86,10 @@ enum {
                              key; finds are FIND_NAIVE (FindSimple) or
                              FIND_TWO_TRY_SPLIT.  Roots are not component minima,
                              so labels come from a separate minimum reduction.
-                             Sampling: none or k-out; the workspace holds the words
-                             (8 bytes per vertex).  Not in batched or served calls. */
+                             Sampling: none or k-out (one lane per vertex; the
+                             schedule, pre-link and local-first options do not
+                             apply); the workspace holds the words (8 bytes per
+                             vertex).  Not in batched or served calls.         */
 };
 
 /* On-the-fly compression inside Find (Appendix A.2, find options). */
