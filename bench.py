@@ -39,6 +39,8 @@ PHASE_KERNEL = {"init_ms": "k_init", "sample_ms": "k_sample_kout_pf", "lmax_ms":
 
 def sample_kernels(args) -> str:
     """The kernel(s) of the k-out sampling phase for these options."""
+    if args.link == "jtb":
+        return "k_jtb_kout"
     if args.kout_local or args.schedule == "twopass":
         return "k_kout_local+k_kout_residual"
     if args.kout_prelink:
