@@ -516,10 +516,13 @@ def other_configs_bench(G, args) -> dict:
         for cfg in cfgs:
             o = G.Options(**cfg)
             ws = G.alloc_workspace(G.workspace_size(dg, o))
+            t_first = time.perf_counter()
             _, st = G.cc(dg, labels=lab, options=o, workspace=ws, stats=True)
+            t_first = time.perf_counter() - t_first
             ok = labels_sha(G.to_u32(lab)) == gold["labels_sha256"] if gold else None
-            reps = 5
-            G.cc(dg, labels=lab, options=o, workspace=ws)
+            reps = 5 if t_first < 0.2 else 1  # label propagation on a grid takes seconds
+            if reps > 1:
+                G.cc(dg, labels=lab, options=o, workspace=ws)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
@@ -527,7 +530,7 @@ def other_configs_bench(G, args) -> dict:
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / reps
             run = {**cfg, "ms": round(ms, 4), "gedges_per_s": round(C.m / (ms * 1e-3) / 1e9, 2),
-                   "rounds": st["rounds"], "labels_match_oracle_golden": ok}
+                   "rounds": st["rounds"], "reps": reps, "labels_match_oracle_golden": ok}
             if cfg["link"] not in ("sv", "lt", "lp"):
                 # the same pipeline captured once into a HIP graph, replayed
                 ex = G.capture_cc(dg, lab, options=o, workspace=ws)

@@ -201,13 +201,14 @@ struct gconn_server {
     // need not wait for earlier epochs and overlap the kernels still running
     // there.  Large pageable inputs are staged in chunks, so that the host
     // copy of one chunk overlaps the transfer of the previous one; pinned
-    // inputs are read by the copy engines directly.
+    // inputs are read by the copy engines directly, one transfer per array.
     uint32_t* ha = reinterpret_cast<uint32_t*>(host);
     uint32_t* hb = ha + r.count;
     const uint32_t* sa = r.pinned_in ? r.a : ha;
     const uint32_t* sb = r.pinned_in ? r.b : hb;
-    for (uint64_t lo = 0; lo < r.count; lo += kInsertChunk) {
-      const uint64_t len = std::min<uint64_t>(kInsertChunk, r.count - lo);
+    const uint64_t chunk = r.pinned_in ? std::max<uint64_t>(r.count, 1) : kInsertChunk;
+    for (uint64_t lo = 0; lo < r.count; lo += chunk) {
+      const uint64_t len = std::min<uint64_t>(chunk, r.count - lo);
       if (!r.pinned_in) {
         staged_copy(ha + lo, r.a + lo, 4 * len);
         staged_copy(hb + lo, r.b + lo, 4 * len);
