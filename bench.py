@@ -160,6 +160,8 @@ def finish_rules_bench(G, args, dg, n: int, m: int, gold_sha) -> dict:
     import torch
     dev = torch.device("cuda", 0)
     cfgs = [dict(link="rem_cas", find="split", splice="split_one"),
+            dict(link="rem_cas", find="split", splice="halve_one"),
+            dict(link="rem_cas", find="split", splice="splice_atomic"),
             dict(link="async", find="halve"), dict(link="async", find="split"),
             dict(link="early", find="halve"), dict(link="hooks", find="split"),
             dict(link="rem_lock", find="split"), dict(link="ecl"), dict(link="afforest"),
