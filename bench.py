@@ -612,11 +612,13 @@ def main() -> int:
     ap.add_argument("--sample", default="kout")
     ap.add_argument("--link", default="rem_cas")
     ap.add_argument("--find", default="split")
-    ap.add_argument("--splice", default="split_one")
+    ap.add_argument("--splice", default="splice_atomic",
+                    help="Union-Rem-CAS splice rule (the spanning-forest leg uses split_one "
+                         "when this is splice_atomic, which links non-roots)")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--kout-prelink", type=int, default=0, choices=(0, 1))
     ap.add_argument("--kout-local", type=int, default=0, choices=(0, 1))
-    ap.add_argument("--schedule", default="twopass", choices=("auto", "lane", "step", "pipe", "twopass"),
+    ap.add_argument("--schedule", default="auto", choices=("auto", "lane", "step", "pipe", "twopass"),
                     help="k-out kernel schedule (twopass: rows streamed to a slot array, then "
                          "the union pass over the slots)")
     ap.add_argument("--atomic-compress", type=int, default=1, choices=(0, 1))
@@ -815,9 +817,15 @@ def main() -> int:
     if not args.no_extras:
         fu = torch.empty(n, dtype=torch.int32, device=dev)
         fv = torch.empty(n, dtype=torch.int32, device=dev)
-        ws_f = G.alloc_workspace(G.workspace_size(dg, opts, forest=True, labels=False))
+        # a forest needs root-based links: Rem's SpliceAtomic re-hangs non-roots
+        sf_splice = "split_one" if args.splice == "splice_atomic" else args.splice
+        sf_opts = G.Options(sample=args.sample, link=args.link, find=args.find, splice=sf_splice,
+                            block=args.block, kout_prelink=bool(args.kout_prelink),
+                            kout_local=bool(args.kout_local), schedule=args.schedule,
+                            atomic_compress=bool(args.atomic_compress))
+        ws_f = G.alloc_workspace(G.workspace_size(dg, sf_opts, forest=True, labels=False))
         lib = G.lib()
-        o = opts.to_c()
+        o = sf_opts.to_c()
         import ctypes
 
         def sf_step():
@@ -835,7 +843,7 @@ def main() -> int:
         filled = int((fu != -1).sum().item())
         comps = int((torch.from_numpy(got.view(np.int32)).to(dev) ==
                      torch.arange(n, dtype=torch.int32, device=dev)).sum().item())
-        result["spanning_forest"] = {"ms_per_step": round(sf_ms, 5),
+        result["spanning_forest"] = {"splice": sf_splice, "ms_per_step": round(sf_ms, 5),
                                      "gedges_per_s": round(m / (sf_ms * 1e-3) / 1e9, 2),
                                      "forest_edges": filled, "n_minus_c": n - comps}
         log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")

@@ -164,6 +164,15 @@ struct gconn_server {
   uint64_t epoch = 0;
   int rr = 0;
 
+  // Frees the HIP resources the server created (also after a failed create).
+  // The worker thread, if it was started, has been joined before this runs.
+  ~gconn_server() {
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    for (auto e : fences) (void)hipEventDestroy(e);
+    for (auto e : event_pool) (void)hipEventDestroy(e);
+    if (staging) (void)hipHostFree(staging);
+  }
+
   double now_us() const {
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   }
@@ -341,15 +350,16 @@ gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* paren
   s->arena = static_cast<uint8_t*>(arena);
   s->space = RangeAlloc(cfg->arena_bytes / kGranule * kGranule);
   GCONN_HIP(hipGetDevice(&s->device));
-  GCONN_HIP(hipHostMalloc(reinterpret_cast<void**>(&s->staging), cfg->arena_bytes,
-                          hipHostMallocDefault));
+  void* staging = nullptr;
+  GCONN_HIP(hipHostMalloc(&staging, cfg->arena_bytes, hipHostMallocDefault));
+  s->staging = static_cast<uint8_t*>(staging);
   for (uint32_t t = 0; t < s->cfg.streams; ++t) {
     hipStream_t st = nullptr;
     GCONN_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     s->streams.push_back(st);
     hipEvent_t e = nullptr;
     GCONN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    s->fences.push_back(e);
+    s->fences.push_back(e);  // on any failure above, s's destructor frees what exists
   }
   s->inflight.resize(s->streams.size());
   GCONN_TRY(launch_iota(parent_buf, cfg->n_max, s->streams[0]));
@@ -427,10 +437,6 @@ gconn_status gconn_server_destroy(gconn_server* s) {
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  for (auto st : s->streams) (void)hipStreamDestroy(st);
-  for (auto e : s->fences) (void)hipEventDestroy(e);
-  for (auto e : s->event_pool) (void)hipEventDestroy(e);
-  if (s->staging) (void)hipHostFree(s->staging);
   delete s;
   return GCONN_OK;
 }

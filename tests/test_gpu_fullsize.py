@@ -23,7 +23,8 @@ WORK = {"rmat24_ef16_s1": lambda: graphgen.rmat(24, 16, 1),
         "er_n100000_m1000000_s1": lambda: graphgen.er(100_000, 1_000_000, 1),
         "grid2d_4096_p07_s1": lambda: graphgen.grid2d(4096, 4096, 0.7, 1),
         "grid3d_256_p06_s1": lambda: graphgen.grid3d(256, 256, 256, 0.6, 1)}
-CONFIGS = [dict(sample="kout", link="rem_cas", find="split", splice="split_one"),  # benchmark
+CONFIGS = [dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic"),  # benchmark
+           dict(sample="kout", link="rem_cas", find="split", splice="split_one"),  # its forest
            dict(sample="kout", link="rem_cas", find="halve", kout_prelink=True),
            dict(sample="kout", link="rem_cas", find="split", kout_local=True),
            dict(sample="kout", link="rem_cas", find="split", schedule="twopass"),
