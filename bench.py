@@ -261,9 +261,10 @@ def insert_slices(src, dst, lo, hi):
     return src[lo:hi], dst[lo:hi]
 
 
-def incremental_bench(G, n, src, dst, reqs, args) -> dict:
+def incremental_bench(G, n, src, dst, reqs, args, rule=None) -> dict:
     """Device-resident replay of the update stream: all batches already in HBM,
-    one gconn_inc_* call per request on one stream, HIP events per batch."""
+    one gconn_inc_* call per request on one stream, HIP events per batch.
+    rule: union-find options (default Union-Async + FindSplit)."""
     import numpy as np
     import torch
     dev = torch.device("cuda", 0)
@@ -272,7 +273,8 @@ def incremental_bench(G, n, src, dst, reqs, args) -> dict:
     qs = [(torch.from_numpy(a.view(np.int32)).to(dev), torch.from_numpy(b.view(np.int32)).to(dev))
           for k, a, b in reqs if k == 1]
     qout = torch.empty(100_000, dtype=torch.uint8, device=dev)
-    inc = G.Incremental(n, options=G.Options(sample="none", link="async", find="split"))
+    rule = rule or dict(link="async", find="split")
+    inc = G.Incremental(n, options=G.Options(sample="none", **rule))
     torch.cuda.synchronize()
     evs, qi = [], 0
     w0 = time.perf_counter()
@@ -878,6 +880,17 @@ def main() -> int:
                         f"batches, log-uniform 1e4..1e7) with {len(reqs) - n_ins} query batches "
                         "of 1e5 uniform pairs interleaved by coin flip; Union-Async + FindSplit",
             "device_resident": incremental_bench(G, sn, ssrc, sdst, reqs, args)}
+        # the other union-find rules on the same device-resident stream
+        rules = {}
+        for rule in (dict(link="rem_cas", find="split", splice="splice_atomic"),
+                     dict(link="rem_cas", find="split", splice="split_one"),
+                     dict(link="early", find="halve"), dict(link="hooks", find="split"),
+                     dict(link="jtb", find="two_try_split")):
+            r = incremental_bench(G, sn, ssrc, sdst, reqs, args, rule)
+            rules["+".join(rule.values())] = {k: r[k] for k in (
+                "insert_updates_per_s", "insert_batch_ms_p99", "query_batch_ms_p99",
+                "label_invariants_hold")}
+        result["incremental"]["device_resident_rules"] = rules
         log(f"incremental stream built in {time.time() - t0:.1f}s: {result['incremental']}")
         if not args.no_serving:
             result["incremental"]["host_fed_server"] = serving_bench(G, sn, ssrc, sdst, reqs, args)

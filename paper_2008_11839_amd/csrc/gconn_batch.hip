@@ -23,7 +23,9 @@ namespace gconn {
 
 // Union-find rules available per class, by rule id: 0-2 Union-Async with
 // FindNaive / FindSplit / FindHalve, 3-5 Union-Rem-CAS with SplitAtomicOne and
-// those finds, 6-8 the same with HalveAtomicOne, 9-11 Union-Early.
+// those finds, 6-8 the same with HalveAtomicOne, 9-11 Union-Early, 12-14
+// Union-Rem-CAS with Rem's SpliceAtomic (unions and finds are never concurrent
+// in a batch run: sampling, gathering and finishing are separate kernels).
 
 __device__ __forceinline__ bool unite_by_id(uint32_t rid, const LinkCtx& c, uint32_t u,
                                             uint32_t v) {
@@ -39,7 +41,10 @@ __device__ __forceinline__ bool unite_by_id(uint32_t rid, const LinkCtx& c, uint
     case 8: return Rule<kUnionRemCas, kFindHalve, kSpliceHalveOne>::unite(c, u, v);
     case 9: return Rule<kUnionEarly, kFindNaive, 0>::unite(c, u, v);
     case 10: return Rule<kUnionEarly, kFindSplit, 0>::unite(c, u, v);
-    default: return Rule<kUnionEarly, kFindHalve, 0>::unite(c, u, v);
+    case 11: return Rule<kUnionEarly, kFindHalve, 0>::unite(c, u, v);
+    case 12: return Rule<kUnionRemCas, kFindNaive, kSpliceAtomic>::unite(c, u, v);
+    case 13: return Rule<kUnionRemCas, kFindSplit, kSpliceAtomic>::unite(c, u, v);
+    default: return Rule<kUnionRemCas, kFindHalve, kSpliceAtomic>::unite(c, u, v);
   }
 }
 
@@ -260,6 +265,10 @@ gconn_status rule_id(const gconn_class_options& c, uint32_t* rid) {
   switch (c.link) {
     case GCONN_LINK_ASYNC: *rid = (uint32_t)f; return GCONN_OK;
     case GCONN_LINK_REM_CAS:
+      if (c.splice == GCONN_SPLICE_ATOMIC) {
+        *rid = 12 + (uint32_t)f;
+        return GCONN_OK;
+      }
       if (c.splice != GCONN_SPLICE_SPLIT_ONE && c.splice != GCONN_SPLICE_HALVE_ONE)
         return fail(GCONN_EINVAL, "class splice out of range");
       *rid = 3 + (c.splice == GCONN_SPLICE_HALVE_ONE ? 3u : 0u) + (uint32_t)f;

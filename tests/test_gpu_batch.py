@@ -37,6 +37,9 @@ CLASS_SETS = [
      dict(sample="kout", link="rem_cas", find="halve", splice="halve_one", k=3),
      dict(sample="kout", link="early", find="naive", k=1),
      dict(sample="none", link="rem_cas", find="naive", splice="split_one")],
+    [dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic", k=2),
+     dict(sample="none", link="rem_cas", find="halve", splice="splice_atomic"),
+     dict(sample="kout", link="rem_cas", find="naive", splice="splice_atomic", k=3)],
 ]
 
 
