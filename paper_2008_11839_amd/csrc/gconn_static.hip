@@ -652,15 +652,38 @@ template <typename OffT>
 __global__ void k_compress_gather(const OffT* __restrict__ off, uint32_t* P, uint32_t n, Ctrl* c,
                                   WorkLists wl, int mode, int skip_lmax, int want_stats) {
   const uint32_t lmax = skip_lmax ? c->lmax : kEmpty;
+  // 16-byte loads of a lane's four offsets and parents when they are aligned
+  // (uint32 offsets, 16-byte aligned arrays, four vertices in range).
+  const bool vec = sizeof(OffT) == 4 &&
+                   ((reinterpret_cast<uintptr_t>(off) | reinterpret_cast<uintptr_t>(P)) % 16) == 0;
   unsigned long long act = 0, edges = 0;
   for (uint64_t base = wave_base() * 4; base < n; base += wave_stride() * 4) {
     const uint64_t v0 = base + 4 * lane();
     uint64_t o[5];
     uint32_t p[4], r[4];
+    if (vec && v0 + 4 <= n) {
+      const uint4 oo = *reinterpret_cast<const uint4*>(off + v0);
+      o[0] = oo.x;
+      o[1] = oo.y;
+      o[2] = oo.z;
+      o[3] = oo.w;
+      o[4] = (uint64_t)off[v0 + 4];  // off has n + 1 entries
+      if (mode != 0) {
+        const uint4 pp = *reinterpret_cast<const uint4*>(P + v0);
+        p[0] = pp.x;
+        p[1] = pp.y;
+        p[2] = pp.z;
+        p[3] = pp.w;
+      } else {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) o[k] = (v0 + k <= n) ? (uint64_t)off[v0 + k] : 0;
+        for (int k = 0; k < 4; ++k) p[k] = (uint32_t)(v0 + k);
+      }
+    } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) p[k] = (mode != 0 && v0 + k < n) ? P[v0 + k] : (uint32_t)(v0 + k);
+      for (int k = 0; k < 5; ++k) o[k] = (v0 + k <= n) ? (uint64_t)off[v0 + k] : 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] = (mode != 0 && v0 + k < n) ? P[v0 + k] : (uint32_t)(v0 + k);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) r[k] = p[k];
     if (mode == 2) {
