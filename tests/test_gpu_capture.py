@@ -15,7 +15,8 @@ from tests import graphs as tg
 
 pytestmark = pytest.mark.gpu
 
-RULES = [dict(sample="kout", link="rem_cas", find="split", splice="split_one"),
+RULES = [dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic"),
+         dict(sample="kout", link="rem_cas", find="split", splice="split_one"),
          dict(sample="kout", link="async", find="halve"),
          dict(sample="kout", link="rem_cas", find="halve", kout_prelink=True),
          dict(sample="hb", link="early", find="split"),
