@@ -67,7 +67,8 @@ struct WsLayout {
   size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
   size_t resid = 0;   // k-out pre-link: residual sampled edges (uint2[n])
   size_t words = 0;   // Union-JTB (rank, parent) words (uint64[n])
-  size_t roots = 0;   // Union-JTB flat roots, then component minima (uint32[n])
+  size_t roots = 0;   // Union-JTB flat roots after sampling (uint32[n])
+  size_t mins = 0;    // Union-JTB component minima for the labels (uint32[n])
   uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;

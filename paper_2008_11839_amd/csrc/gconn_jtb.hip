@@ -29,8 +29,10 @@ __device__ __forceinline__ uint32_t jtb_root_plain(const uint64_t* W, uint32_t x
 }
 
 // Clears the control block (block 0) and makes every vertex a rank-0 root;
-// empties the forest slots when they are given.
-__global__ void k_jtb_init(Ctrl* c, uint64_t* W, uint32_t n, uint32_t* fu, uint32_t* fv) {
+// empties the forest slots when they are given; sets M to the identity when
+// it is given (the component minima of the final labelling start there).
+__global__ void k_jtb_init(Ctrl* c, uint64_t* W, uint32_t n, uint32_t* fu, uint32_t* fv,
+                           uint32_t* M) {
   if (c && blockIdx.x == 0) {
     uint32_t* w = reinterpret_cast<uint32_t*>(c);
     for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
@@ -43,6 +45,7 @@ __global__ void k_jtb_init(Ctrl* c, uint64_t* W, uint32_t n, uint32_t* fu, uint3
   }
   for (uint64_t v = gtid(); v < n; v += wave_stride()) {
     W[v] = jtb_word((uint32_t)v, 0);
+    if (M) M[v] = (uint32_t)v;
     if (fu) {
       fu[v] = kEmpty;
       fv[v] = kEmpty;
@@ -195,25 +198,22 @@ __global__ void k_jtb_query(const uint8_t* __restrict__ kind, const uint32_t* __
   }
 }
 
-// Canonical labels, pass 1: L[v] = root(v); M[v] = v.
-__global__ void k_jtb_roots(const uint64_t* W, uint32_t* L, uint32_t* M, uint32_t n) {
-  for (uint64_t v = gtid(); v < n; v += wave_stride()) {
-    L[v] = jtb_root_plain(W, (uint32_t)v);
-    M[v] = (uint32_t)v;
-  }
-}
-
-// Pass 2: M[r] = min over the component of root r.  M[r] starts at r, so only
-// vertices below their root take part.  In a wave, the lowest such lane of
-// each root holds that root's smallest id in the wave (ids rise with the
-// lane), so one lane per distinct root writes; it skips the atomic when M[r]
-// is already at most its id (M only decreases, so any value read is an upper
-// bound of the current one).  The grid runs roughly in id order, so the giant
-// component's minimum lands early and later waves skip.
-__global__ void k_jtb_min(const uint32_t* L, uint32_t* M, uint32_t n) {
+// Canonical labels, pass 1: L[v] = root(v), and M[r] = the minimum over the
+// component of root r (M starts as the identity).  Only vertices below their
+// root can lower M[r].  In a wave, the lowest such lane of each root holds
+// that root's smallest id in the wave (ids rise with the lane), so one lane
+// per distinct root writes; it skips the atomic when M[r] is already at most
+// its id (M only decreases, so any value read is an upper bound of the current
+// one).  The grid runs roughly in id order, so the giant component's minimum
+// lands early and later waves skip.
+__global__ void k_jtb_roots_min(const uint64_t* W, uint32_t* L, uint32_t* M, uint32_t n) {
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
     const uint64_t v = base + lane();
-    const uint32_t r = v < n ? L[v] : 0u;
+    uint32_t r = 0;
+    if (v < n) {
+      r = jtb_root_plain(W, (uint32_t)v);
+      L[v] = r;
+    }
     bool pending = v < n && v < r;
     unsigned long long mask = __ballot(pending);
     while (mask) {
@@ -226,7 +226,7 @@ __global__ void k_jtb_min(const uint32_t* L, uint32_t* M, uint32_t n) {
   }
 }
 
-// Pass 3: L[v] = M[L[v]].
+// Pass 2: L[v] = M[L[v]].
 __global__ void k_jtb_relabel(uint32_t* L, const uint32_t* M, uint32_t n) {
   for (uint64_t v = gtid(); v < n; v += wave_stride()) L[v] = M[L[v]];
 }
@@ -238,13 +238,13 @@ gconn_status with_jtb_find(int find_rule, Fn&& fn) {
   return fn(std::integral_constant<int, kJtbFindSimple>{});
 }
 
+// M: n entries; m_ready: M already holds the identity (else it is set here).
 gconn_status jtb_labels(const uint64_t* W, uint32_t n, uint32_t* labels, uint32_t* M, uint32_t block,
-                        hipStream_t s) {
+                        bool m_ready, hipStream_t s) {
   const uint32_t grid = grid_for(n, block);
-  k_jtb_roots<<<grid, block, 0, s>>>(W, labels, M, n);
-  GCONN_LAUNCHED("k_jtb_roots");
-  k_jtb_min<<<grid, block, 0, s>>>(labels, M, n);
-  GCONN_LAUNCHED("k_jtb_min");
+  if (!m_ready) GCONN_TRY(launch_iota(M, n, s));
+  k_jtb_roots_min<<<grid, block, 0, s>>>(W, labels, M, n);
+  GCONN_LAUNCHED("k_jtb_roots_min");
   k_jtb_relabel<<<grid, block, 0, s>>>(labels, M, n);
   GCONN_LAUNCHED("k_jtb_relabel");
   return GCONN_OK;
@@ -276,6 +276,7 @@ WsLayout plan_workspace_jtb(const gconn_graph& g, const gconn_options& o, bool f
   if (forest && !labels) L.P = take(4 * n);
   L.words = take(8 * n);
   L.roots = take(4 * n);
+  if (labels) L.mins = take(4 * n);
   if (g.format == GCONN_CSR) {
     // one push call per 64-vertex group; group g goes to sub-list g % kSubLists
     const uint64_t groups = (n + 63) / 64;
@@ -302,7 +303,8 @@ gconn_status run_static_jtb(const gconn_graph& g, uint32_t* P, uint32_t* fu, uin
   const bool sampled = csr && o.sample == GCONN_SAMPLE_KOUT;
   prof_count_run();
   GCONN_TRY(prof_mark(kPhaseInit, true, s));
-  k_jtb_init<<<grid_for(std::max<uint32_t>(n, 1), block), block, 0, s>>>(ctrl, W, n, fu, fv);
+  uint32_t* M = finalize ? reinterpret_cast<uint32_t*>(ws + L.mins) : nullptr;
+  k_jtb_init<<<grid_for(std::max<uint32_t>(n, 1), block), block, 0, s>>>(ctrl, W, n, fu, fv, M);
   GCONN_LAUNCHED("k_jtb_init");
   GCONN_TRY(prof_mark(kPhaseInit, false, s));
   if (o.validate && (g.m > 0 || csr)) GCONN_TRY(validate_graph(g, ctrl, block, s));
@@ -354,7 +356,7 @@ gconn_status run_static_jtb(const gconn_graph& g, uint32_t* P, uint32_t* fu, uin
   }
   if (finalize && n > 0) {
     GCONN_TRY(prof_mark(kPhaseFinalize, true, s));
-    GCONN_TRY(jtb_labels(W, n, P, R, block, s));
+    GCONN_TRY(jtb_labels(W, n, P, M, block, true, s));
     GCONN_TRY(prof_mark(kPhaseFinalize, false, s));
   }
   if (stats) {
@@ -374,7 +376,7 @@ gconn_status run_static_jtb(const gconn_graph& g, uint32_t* P, uint32_t* fu, uin
 
 gconn_status launch_jtb_init(uint64_t* W, uint32_t n, hipStream_t s) {
   if (n == 0) return GCONN_OK;
-  k_jtb_init<<<grid_for(n, 256), 256, 0, s>>>(nullptr, W, n, nullptr, nullptr);
+  k_jtb_init<<<grid_for(n, 256), 256, 0, s>>>(nullptr, W, n, nullptr, nullptr, nullptr);
   GCONN_LAUNCHED("k_jtb_init");
   return GCONN_OK;
 }
@@ -421,7 +423,7 @@ gconn_status launch_jtb_mixed(const gconn_options& o, uint64_t* W, const uint8_t
 gconn_status launch_jtb_labels(const uint64_t* W, uint32_t n, uint32_t* labels, uint32_t* scratch,
                                hipStream_t s) {
   if (n == 0) return GCONN_OK;
-  return jtb_labels(W, n, labels, scratch, 256, s);
+  return jtb_labels(W, n, labels, scratch, 256, false, s);
 }
 
 }  // namespace gconn
