@@ -89,16 +89,16 @@ def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
 def jtb_bytes(n: int, st: dict) -> int:
     """Algorithmic bytes of the Union-JTB pipeline (8-byte (rank, parent) words).
 
-    init: write W (8n).  k-out: offsets (4n) and, per sampled entry, the
-    neighbour id plus two words (20 B).  flatten: read W, write the roots (12n).
-    gather: offsets (4n), the roots when sampled (4n), the list (4A).  finish:
-    offsets of the active vertices (8A) and 20 B per entry.  links: one 8-byte
-    CAS per hook (8H).  canonical labels: roots (read W, write labels and M:
-    16n), minima (read labels: 4n), relabel (read labels, gather M, write: 12n).
+    init: write W and the minima M (12n).  k-out: offsets (4n) and, per sampled
+    entry, the neighbour id plus two words (20 B).  flatten: read W, write the
+    roots (12n).  gather: offsets (4n), the roots when sampled (4n), the list
+    (4A).  finish: offsets of the active vertices (8A) and 20 B per entry.
+    links: one 8-byte CAS per hook (8H).  canonical labels: roots and minima
+    (read W, write labels: 12n), relabel (read labels, gather M, write: 12n).
     """
     Es, A, Ef, H = (st["sampled_edges"], st["active_vertices"], st["finish_edges"],
                     st["hooks"])
-    base = 8 * n + 20 * Ef + 12 * A + 8 * H + 32 * n + 4 * n
+    base = 12 * n + 20 * Ef + 12 * A + 8 * H + 24 * n + 4 * n
     if Es:
         base += 4 * n + 20 * Es + 12 * n + 4 * n
     return base
