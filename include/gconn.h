@@ -159,7 +159,11 @@ typedef struct gconn_options {
                             every vertex's sampled neighbours to a slot array,
                             then the union pass runs over the slots, so its
                             lanes start on unions at once (first k <= 2; else
-                            as 0)                                           (0) */
+                            as 0), 5 flat: the pre-link pass (kout_prelink),
+                            then a pass that points every vertex at its
+                            pre-link tree's root, then the union pass over
+                            the remaining sampled edges, starting from roots
+                            (first k <= 2; else as 0)                      (0) */
   int32_t atomic_compress; /* path-compression and splice writes (FindSplit,
                             FindHalve, SplitAtomicOne, HalveAtomicOne, the
                             Union-Early splice): 1 CAS as in the atomic rules,
@@ -388,8 +392,11 @@ gconn_status gconn_server_create(const gconn_server_config* cfg, uint32_t* paren
  * queries only: 1 iff connected) must stay valid until the request is done.
  * Pageable buffers go through the server's pinned staging area; buffers that
  * are pinned already (hipHostMalloc, torch pin_memory) are read and written
- * by the copy engines directly, with no host copy.  Returns GCONN_EINVAL for a
- * request larger than the arena.  Thread-safe. */
+ * by the copy engines directly, with no host copy.  Returns GCONN_EINVAL, and
+ * queues nothing, for a request larger than the arena or one holding a vertex
+ * id >= n_max (submission scans the ids on the host whatever
+ * options.validate says: the parent array is shared by every client, so one
+ * bad id must not reach the kernels).  Thread-safe. */
 gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, const uint32_t* b,
                                  uint64_t count, uint8_t* out, uint64_t* ticket);
 /* Blocks until the request is done or timeout_s (< 0: no limit) elapses

@@ -3,29 +3,49 @@
 //
 // P[x] == x marks a root; every other P[x] points to a smaller id in the same
 // tree (Notation and Preliminaries: elements point to themselves or to a parent
-// with a smaller ID).  All rules are root-based: a CAS only ever turns a root
-// into a child, always of a smaller id, so no cycle can form.
+// with a smaller ID).  Every write stores a smaller id than the slot's owner
+// (and than the value it replaces), so no cycle can form.  All rules but Rem's
+// SpliceAtomic are root-based: a link only ever turns a root into a child.
 //
 // Memory model.  The eight XCDs of an MI355X each have a private L2 that is
 // not kept coherent with the others inside a kernel.  Links (a root becoming a
 // child) are agent-scope CAS.  Reads of P inside find / union loops are relaxed
 // atomic loads whose scope is GCONN_P_LOAD_SCOPE; at wavefront or workgroup
 // scope they are ordinary cached loads (L2 hits for the hot entries near the
-// roots of large trees) and may return stale values.  Correctness never
-// depends on a read being fresh: any value P[x] has ever held is an ancestor
-// of x in the current forest, and every link is a CAS that re-validates.
-// Progress does not depend on it either: every loop iteration below either
-// moves to a strictly smaller id, or continues from the value a failed CAS
-// returned (which is fresh), so no loop can spin on a stale line.
+// roots of large trees) and may return stale values.  Two invariants make
+// that safe, and they differ between the rule families:
+//   * Root-based rules (every union rule below except Rem's SpliceAtomic):
+//     only roots are re-pointed by links, and compression only moves a
+//     non-root's pointer to one of its ancestors.  So any value P[x] has ever
+//     held is an ancestor of x in the current forest, and a walk may start
+//     from any of them, stale or not.
+//   * Rem's SpliceAtomic re-hangs a non-root (with its subtree) under the
+//     other side's parent, moving it out of its ancestors' tree; an old value
+//     of P[x] is then no longer an ancestor of x.  What still holds is weaker:
+//     P[x] only ever decreases (every write stores a smaller id), and every
+//     value it has held belongs to the set x ends up in once the unions of
+//     the phase are done (a splice is part of a union that goes on to join
+//     the two sides).  The ancestry argument does not cover this rule, so it
+//     reads both parents device-coherently on every iteration, and its
+//     trailing compressing finds rely on the CAS instead: a split CAS on P[x]
+//     succeeds only if P[x] still holds the value the walk read, so the value
+//     written is the current parent's parent, whatever an earlier read saw.
+// Progress: every loop iteration below either moves to a strictly smaller
+// id, or continues from the value a failed CAS returned (which is fresh), so
+// no loop can spin on a stale line.  Coherent reads are needed only where a
+// stale value could send a lane back to a CAS that is bound to fail again
+// (Union-Hooks' root test, the splice and lock rules).
 //
-// Compression writes (the splitting / halving steps of the finds and the
-// splice steps) only ever touch a non-root x and set P[x] to an ancestor of x.
+// Compression writes of the root-based rules (the splitting / halving steps of
+// the finds and the SplitAtomicOne / HalveAtomicOne steps) only ever touch a
+// non-root x and set P[x] to an ancestor of x.
 // A non-root never becomes a root again and no link targets it, so such a
 // write needs no CAS: whatever order concurrent compression writes land in,
 // P[x] ends as some ancestor of x, which is all the forest needs.  With
 // LinkCtx::atomic_compress == 0 they are relaxed agent-scope stores, which
 // write through to memory like the atomics do; with 1 they are the CASes of
-// the atomic rules as written.  They must not be ordinary cached stores: an
+// the atomic rules as written (always so next to SpliceAtomic, whose moves
+// break the ancestor argument).  They must not be ordinary cached stores: an
 // XCD's L2 writes a dirty line back later, and on MI355X that write-back has
 // been measured to undo links that other XCDs made meanwhile on other words
 // of the same line (wrong labels at RMAT-24 scale).

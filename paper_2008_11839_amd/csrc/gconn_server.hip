@@ -64,6 +64,34 @@ void staged_copy(void* dst, const void* src, size_t bytes) {
   for (auto& t : ts) t.join();
 }
 
+// Largest vertex id of a request's two host arrays, split over a few threads
+// for large requests like the staging copy.  Every id reaches the device
+// kernels unchecked, and the parent array is shared by every client of the
+// server, so submission rejects ids >= n_max before anything is queued.
+uint32_t host_max_id(const uint32_t* a, const uint32_t* b, uint64_t count) {
+  auto part_max = [](const uint32_t* x, const uint32_t* y, uint64_t lo, uint64_t hi) {
+    uint32_t m = 0;
+    for (uint64_t i = lo; i < hi; ++i) {
+      const uint32_t t = x[i] > y[i] ? x[i] : y[i];
+      m = t > m ? t : m;
+    }
+    return m;
+  };
+  constexpr uint64_t kPart = 1u << 20;
+  const uint64_t parts = std::min<uint64_t>(8, count / kPart);
+  if (parts < 2) return part_max(a, b, 0, count);
+  std::vector<uint32_t> got(parts, 0);
+  std::vector<std::thread> ts;
+  const uint64_t per = (count + parts - 1) / parts;
+  for (uint64_t i = 1; i < parts; ++i) {
+    const uint64_t lo = i * per, hi = std::min(count, lo + per);
+    ts.emplace_back([&, i, lo, hi] { got[i] = part_max(a, b, lo, hi); });
+  }
+  got[0] = part_max(a, b, 0, std::min(count, per));
+  for (auto& t : ts) t.join();
+  return *std::max_element(got.begin(), got.end());
+}
+
 // First-fit allocator over [0, size) with coalescing of free ranges.
 class RangeAlloc {
  public:
@@ -378,6 +406,10 @@ gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, c
     return fail(GCONN_EINVAL, "kind must be GCONN_REQ_INSERT or GCONN_REQ_QUERY");
   if (count > 0 && (!a || !b)) return fail(GCONN_EINVAL, "a and b are required");
   if (kind == GCONN_REQ_QUERY && count > 0 && !out) return fail(GCONN_EINVAL, "out is required");
+  if (footprint(kind, count) > s->cfg.arena_bytes)
+    return fail(GCONN_EINVAL, "request larger than the server arena");
+  if (count > 0 && host_max_id(a, b, count) >= s->cfg.n_max)
+    return fail(GCONN_EINVAL, "vertex id >= n_max in the request");
   auto r = std::make_unique<Request>();
   r->kind = kind;
   r->a = a;
@@ -385,8 +417,6 @@ gconn_status gconn_server_submit(gconn_server* s, int kind, const uint32_t* a, c
   r->out = out;
   r->count = count;
   r->bytes = footprint(kind, count);
-  if (r->bytes > s->cfg.arena_bytes)
-    return fail(GCONN_EINVAL, "request larger than the server arena");
   r->info.kind = kind;
   r->info.count = count;
   if (count > 0) {

@@ -191,3 +191,42 @@ def test_server_pinned_buffers_skip_staging(gpu_available):
             if reqs[i][0] == 1:
                 assert np.array_equal(out, want[i]), (streams, i)
         srv.close()
+
+
+def test_server_rejects_out_of_range_ids(gpu_available):
+    """A request holding a vertex id >= n_max is refused at submission
+    (GCONN_EINVAL) and never reaches the device; the server keeps serving the
+    other requests, whose answers equal the oracle's.  The bad id is planted
+    at the start, the middle and the end of a request large enough for the
+    threaded scan."""
+    from paper_2008_11839_amd import gconn as G
+
+    n = 5000
+    srv = G.Server(n, streams=2, arena_bytes=64 << 20,
+                   options=G.Options(sample="none", link="rem_cas", find="split"))
+    rng = np.random.default_rng(3)
+    big = 3 << 20
+    for kind in (G.INSERT, G.QUERY):
+        for where in (0, big // 2, big - 1):
+            a = rng.integers(0, n, size=big).astype(np.uint32)
+            b = rng.integers(0, n, size=big).astype(np.uint32)
+            (a if where % 2 == 0 else b)[where] = n  # one id just out of range
+            say(f"[server-ids] kind={kind} bad at {where}")
+            with pytest.raises(G.GconnError) as e:
+                srv.submit(kind, a, b)
+            assert e.value.status == -1  # GCONN_EINVAL
+        with pytest.raises(G.GconnError):
+            srv.submit(kind, np.array([0xFFFFFFFF], np.uint32), np.array([0], np.uint32))
+    # the server still works: a path over the first 100 ids, then queries
+    src = np.arange(0, 99, dtype=np.uint32)
+    dst = src + 1
+    t = srv.submit(G.INSERT, src, dst)
+    rec, _ = srv.wait(t, timeout=60.0)
+    assert rec["status"] == 0
+    qa = np.array([0, 0, 5, 100, 4999], np.uint32)
+    qb = np.array([99, 100, 50, 101, 0], np.uint32)
+    t = srv.submit(G.QUERY, qa, qb)
+    rec, out = srv.wait(t, timeout=60.0)
+    assert rec["status"] == 0
+    assert out.tolist() == [1, 0, 1, 0, 0]
+    srv.close()

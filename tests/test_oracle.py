@@ -206,10 +206,84 @@ def test_lmax_definition():
         assert oracle.lmax(lab, s, seed) == min(k for k, c in cnt.items() if c == top)
 
 
-def test_active_set_counts():
-    G = graphgen.rmat(12, 8, 1)
-    lab, _ = oracle.sample_kout(G.n, G.offsets, G.nbrs, 2)
-    L = oracle.lmax(lab, 1024, 1)
-    deg = G.degrees()
-    assert oracle.active_count(G.n, G.offsets, lab, L) == int(((lab != L) & (deg > 0)).sum())
-    assert oracle.active_edges(G.n, G.offsets, lab, L) == int(deg[lab != L].sum())
+def _clique_pairs(ids):
+    return [(ids[i], ids[j]) for i in range(len(ids)) for j in range(i + 1, len(ids))]
+
+
+def test_active_set_closed_forms():
+    """Vertex gathering (Finish phase of the static algorithm): the active set
+    is the vertices with degree > 0 whose label is not L_max, and the finish
+    reads their whole rows.  Pinned by closed forms on graphs whose answer
+    follows from their shape, with vertex ids shuffled so no block is
+    contiguous."""
+    # disjoint cliques K50, K3, K7, a star with 9 leaves, a path of 6 vertices,
+    # and 5 isolated vertices
+    sizes = {"k50": 50, "k3": 3, "k7": 7, "star": 10, "path": 6, "iso": 5}
+    n = sum(sizes.values())
+    perm = np.random.default_rng(7).permutation(n).astype(np.uint32)
+    blocks, at = {}, 0
+    for name, sz in sizes.items():
+        blocks[name] = [int(x) for x in perm[at:at + sz]]
+        at += sz
+    pairs = (_clique_pairs(blocks["k50"]) + _clique_pairs(blocks["k3"])
+             + _clique_pairs(blocks["k7"])
+             + [(blocks["star"][0], x) for x in blocks["star"][1:]]
+             + list(zip(blocks["path"][:-1], blocks["path"][1:])))
+    G = graphgen.from_pairs(n, pairs)
+    # labels: the component minimum of each block (the final labels)
+    lab = np.arange(n, dtype=np.uint32)
+    for ids in blocks.values():
+        if ids is blocks["iso"]:
+            continue
+        lab[ids] = min(ids)
+    big = min(blocks["k50"])
+    # L_max = the K50 label: active = K3 + K7 + star + path; rows: a clique
+    # K_s contributes s(s-1) entries, the star 2*9, the path 2*5
+    assert oracle.active_count(n, G.offsets, lab, big) == 3 + 7 + 10 + 6
+    assert oracle.active_edges(n, G.offsets, lab, big) == 3 * 2 + 7 * 6 + 18 + 10
+    # L_max = the star's label: its 10 vertices drop out instead
+    s0 = min(blocks["star"])
+    assert oracle.active_count(n, G.offsets, lab, s0) == 50 + 3 + 7 + 6
+    assert oracle.active_edges(n, G.offsets, lab, s0) == 50 * 49 + 3 * 2 + 7 * 6 + 10
+    # a label that occurs nowhere: every vertex with an edge is active and the
+    # finish reads every entry (isolated vertices never count)
+    none = 0xFFFFFFFF
+    assert oracle.active_count(n, G.offsets, lab, none) == n - 5
+    assert oracle.active_edges(n, G.offsets, lab, none) == 2 * len(pairs)
+    # an isolated vertex's own label as L_max removes nothing
+    iso = blocks["iso"][0]
+    assert oracle.active_count(n, G.offsets, lab, iso) == n - 5
+    assert oracle.active_edges(n, G.offsets, lab, iso) == 2 * len(pairs)
+    # sampled labels that split a component (the K7 cut 4 | 3, the path
+    # 2 | 4): only the vertices labelled L_max drop out, whatever their
+    # component; L_max = the label of the K7's 4-part
+    k7 = blocks["k7"]
+    lab2 = lab.copy()
+    lab2[k7[4:]] = k7[4]
+    lab2[blocks["path"][2:]] = blocks["path"][2]
+    four = int(lab2[k7[0]])
+    assert oracle.active_count(n, G.offsets, lab2, four) == n - 5 - 4
+    assert oracle.active_edges(n, G.offsets, lab2, four) == 2 * len(pairs) - 4 * 6
+
+
+def test_active_set_star_and_path():
+    # a star K_{1,r} labelled 0 except the centre: L_max = 0 leaves only the
+    # centre active, with its r entries
+    for r in (1, 2, 17):
+        G = graphgen.from_pairs(r + 1, [(0, x) for x in range(1, r + 1)])
+        lab = np.zeros(r + 1, np.uint32)
+        lab[0] = 1
+        assert oracle.active_count(r + 1, G.offsets, lab, 0) == 1
+        assert oracle.active_edges(r + 1, G.offsets, lab, 0) == r
+        # the leaves: r vertices of degree 1
+        assert oracle.active_count(r + 1, G.offsets, lab, 1) == r
+        assert oracle.active_edges(r + 1, G.offsets, lab, 1) == r
+    # a path 0-1-...-(L-1) with labels alternating 0/1: L_max = 1 keeps the
+    # even positions: ceil(L/2) vertices, ends have degree 1
+    for L in (2, 3, 10, 11):
+        G = graphgen.from_pairs(L, [(i, i + 1) for i in range(L - 1)])
+        lab = (np.arange(L) % 2).astype(np.uint32)
+        evens = (L + 1) // 2
+        ends_even = 1 + (1 if (L - 1) % 2 == 0 else 0)
+        assert oracle.active_count(L, G.offsets, lab, 1) == evens
+        assert oracle.active_edges(L, G.offsets, lab, 1) == 2 * evens - ends_even
