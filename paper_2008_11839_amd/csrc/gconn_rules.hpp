@@ -86,9 +86,16 @@ enum UnionRule : int {
 #define GCONN_P_LOAD_SCOPE __HIP_MEMORY_SCOPE_WAVEFRONT
 #endif
 
-// Read of P inside a find / union loop (see the memory-model note above).
+// Read of P inside a find / union loop (see the memory-model note above).  A
+// host build may route it through GCONN_HOST_STALE_LOAD(p), a function that
+// is free to return any value *p held earlier: the CPU test harness uses it
+// to model an XCD's incoherent L2 (device code never defines it).
 GCONN_HD uint32_t ld(const uint32_t* p) {
+#if defined(GCONN_HOST_STALE_LOAD) && !defined(__HIP_DEVICE_COMPILE__)
+  return GCONN_HOST_STALE_LOAD(p);
+#else
   return __hip_atomic_load(p, __ATOMIC_RELAXED, GCONN_P_LOAD_SCOPE);
+#endif
 }
 // Device-coherent read (flags and counters polled across XCDs).
 GCONN_HD uint32_t ld_agent(const uint32_t* p) {

@@ -3,6 +3,7 @@
 // on one shared parent array.  Test infrastructure only.
 //
 //   rules_stress <edges.bin> <n> <rule> <threads> <labels.out> [atomic_compress]
+//                [stale_percent]
 // edges.bin: uint32 pairs; rule: 0-3 Async (naive/split/halve/compress),
 // 4-7 Hooks, 8-11 Early, 12-17 Rem-CAS (naive/split/halve x split_one/halve_one),
 // 18-20 Rem-CAS with Rem's splice (naive/split/halve), 21 G_Afforest's link,
@@ -10,13 +11,49 @@
 // 26-27 Union-JTB (FindSimple, FindTwoTrySplit) on 64-bit (rank, parent) words.
 // Writes labels (the minimum vertex of every vertex's tree, uint32) and prints
 // the hook count.
+//
+// stale_percent > 0 models the incoherent L2 of an XCD for the rules' cached
+// reads (ld): every thread keeps a private direct-mapped copy of the parent
+// entries it has read (4096 slots, tagged by address); a read returns the
+// copy, however old, with probability stale_percent / 100 when the slot holds
+// that address, and otherwise reads memory and refreshes the copy.  The
+// thread's own CAS and stores do not update its copy, so it can even read back
+// a value older than one it wrote.  Device-coherent reads (ld_agent) and the
+// atomics always see memory.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <thread>
 #include <vector>
+
+namespace stale {
+struct Line {
+  const uint32_t* tag;
+  uint32_t value;
+};
+static int g_percent = 0;
+thread_local Line t_cache[4096];
+thread_local uint64_t t_rng = 0;
+inline uint32_t next_u32() {
+  if (t_rng == 0) t_rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)(uintptr_t)&t_rng;
+  t_rng ^= t_rng << 13;
+  t_rng ^= t_rng >> 7;
+  t_rng ^= t_rng << 17;
+  return (uint32_t)(t_rng >> 32);
+}
+inline uint32_t load(const uint32_t* p) {
+  Line& l = t_cache[((uintptr_t)p >> 2) & 4095];
+  if (g_percent > 0 && l.tag == p && next_u32() % 100 < (uint32_t)g_percent) return l.value;
+  const uint32_t v = __atomic_load_n(p, __ATOMIC_RELAXED);
+  l.tag = p;
+  l.value = v;
+  return v;
+}
+}  // namespace stale
+#define GCONN_HOST_STALE_LOAD(p) ::stale::load(p)
 
 #include "../../paper_2008_11839_amd/csrc/gconn_jtb.hpp"
 #include "../../paper_2008_11839_amd/csrc/gconn_rules.hpp"
@@ -81,7 +118,8 @@ int jtb_main(const std::vector<uint32_t>& e, uint32_t n, int rule, int threads, 
 }
 
 int main(int argc, char** argv) {
-  if (argc != 6 && argc != 7) return 2;
+  if (argc < 6 || argc > 8) return 2;
+  if (argc == 8) stale::g_percent = atoi(argv[7]);
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 3;
   std::vector<uint32_t> e;
@@ -97,7 +135,7 @@ int main(int argc, char** argv) {
   std::vector<uint32_t> P(n), H(n, kEmpty);
   for (uint32_t v = 0; v < n; ++v) P[v] = v;
   unsigned long long hooks = 0;
-  const uint32_t ac = argc == 7 ? (uint32_t)atoi(argv[6]) : 1u;
+  const uint32_t ac = argc >= 7 ? (uint32_t)atoi(argv[6]) : 1u;
   LinkCtx c{P.data(), H.data(), nullptr, nullptr, &hooks, ac};
   switch (rule) {
     case 0: run<Rule<kUnionAsync, kFindNaive, 0>>(e, c, threads); break;

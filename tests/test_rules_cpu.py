@@ -2,7 +2,9 @@
 for the host and run concurrently from many threads: labels equal the
 oracle's, every parent points to a smaller id (Union-JTB: to a vertex above it
 in the rank order), and exactly n - c links succeed, with compression writes
-as CAS and as relaxed stores."""
+as CAS and as relaxed stores -- and with the rules' cached parent reads
+returning stale values (a per-thread copy that models an XCD's incoherent
+L2), which the memory-model argument of gconn_rules.hpp says is harmless."""
 from __future__ import annotations
 
 import os
@@ -66,3 +68,26 @@ def test_rules_concurrent_on_cpu(harness, tmp_path, rule, atomic_compress):
             got = np.fromfile(out, np.uint32)
             assert np.array_equal(got, want), (name, rule, threads)
             assert int(r.stdout.strip()) == n - c, (name, rule, threads)
+
+
+# Union-JTB keeps its own 64-bit reads; the 32-bit rules all read through ld()
+STALE_RULES = [r for r in RULES if r not in (26, 27)]
+
+
+@pytest.mark.parametrize("stale", [30, 90])
+@pytest.mark.parametrize("rule", STALE_RULES)
+def test_rules_with_stale_cached_reads(harness, tmp_path, rule, stale):
+    for name, n, edges in _graphs():
+        ef = tmp_path / f"{name}.bin"
+        edges.astype(np.uint32).tofile(ef)
+        want = oracle.cc_coo(n, edges[:, 0], edges[:, 1])
+        c = int((want == np.arange(n, dtype=np.uint32)).sum())
+        for threads in (4, 32):
+            out = tmp_path / "labels.bin"
+            r = subprocess.run([harness, str(ef), str(n), str(rule), str(threads), str(out),
+                                "1", str(stale)],
+                               capture_output=True, text=True, timeout=120)
+            assert r.returncode == 0, (name, rule, threads, stale, r.returncode)
+            got = np.fromfile(out, np.uint32)
+            assert np.array_equal(got, want), (name, rule, threads, stale)
+            assert int(r.stdout.strip()) == n - c, (name, rule, threads, stale)
