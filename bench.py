@@ -43,6 +43,8 @@ def sample_kernels(args) -> str:
         return "k_jtb_kout"
     if args.kout_local or args.schedule == "twopass":
         return "k_kout_local+k_kout_residual"
+    if args.schedule == "flat":
+        return "k_kout_prelink+k_flatten+k_kout_residual_flat"
     if args.kout_prelink:
         return "k_kout_prelink+k_kout_residual"
     return {"auto": "k_sample_kout_pf", "lane": "k_sample_kout", "pipe": "k_sample_kout_pipe",
@@ -84,6 +86,74 @@ def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
     return {"init_ms": 4 * n, "sample_ms": 4 * (n + 1) + 12 * Es, "lmax_ms": 4 * samples,
             "gather_ms": 12 * n + 4 + 4 * A, "finish_ms": 8 * A + 12 * Ef,
             "finalize_ms": 12 * A}
+
+
+def step_model_bytes(n: int, st: dict) -> int:
+    """Bytes of one whole static step, sampled union-find path, at 4-byte
+    granularity: init 4n, offsets 4(n+1), 12 B per sampled entry (neighbour id
+    and two parent reads), full compress 8n, gather read 4n, 12 B per active
+    vertex, 12 B per finish entry, a 4-byte write per hook, finalisation 8n:
+    28n + 12(E_s + E_f) + 12A + 4H (+4 for the last offset)."""
+    Es, A, Ef, H = (st["sampled_edges"], st["active_vertices"], st["finish_edges"],
+                    st["hooks"])
+    return 28 * n + 4 + 12 * (Es + Ef) + 12 * A + 4 * H
+
+
+def host_info() -> dict:
+    """CPU model and the cores this process may use (for the oracle timings)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "host_cores": usable, "os_cpu_count": os.cpu_count()}
+
+
+def pool_size() -> int:
+    """Worker threads for graph-parallel oracle runs: the cores this process
+    may use, capped by OMP_NUM_THREADS when it is set (the machine's CPU share)."""
+    usable = host_info()["host_cores"] or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    return max(1, min(usable, int(cap))) if cap and cap.isdigit() else usable
+
+
+def incremental_cpu_baseline(n, src, dst, reqs, budget_s: float = 10.0) -> dict:
+    """The oracle's sequential union-find replaying the update stream from its
+    start on one core, request by request, until budget_s of CPU work has run
+    (or the stream ends): updates per second and per-batch times."""
+    import oracle
+    uf = oracle.UnionFind(n)
+    done, t_ins, t_q, nq = 0, 0.0, 0.0, 0
+    t_start = time.perf_counter()
+    per_batch = []
+    for k, x, y in reqs:
+        t0 = time.perf_counter()
+        if k == 0:
+            a, b = insert_slices(src, dst, x, y)
+            uf.insert(a, b)
+            dt = time.perf_counter() - t0
+            t_ins += dt
+            done += y - x
+            per_batch.append(dt * 1e3)
+        else:
+            uf.query(x, y)
+            t_q += time.perf_counter() - t0
+            nq += len(x)
+        if time.perf_counter() - t_start > budget_s:
+            break
+    return {"value": round(done / t_ins, 1) if t_ins > 0 else None, "unit": "updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"the stream's first {done} updates and {nq} query pairs "
+                      f"(~{budget_s:.0f} s of oracle work)",
+            "query_pairs_per_s": round(nq / t_q, 1) if t_q > 0 else None,
+            "insert_batch_ms_p50": round(percentile(per_batch, 50), 3) if per_batch else None,
+            "insert_batch_ms_p99": round(percentile(per_batch, 99), 3) if per_batch else None,
+            **host_info()}
 
 
 def jtb_bytes(n: int, st: dict) -> int:
@@ -223,42 +293,46 @@ def percentile(xs, p):
 
 
 def update_stream(args):
-    """The incremental workload: an RMAT edge stream (both directions, so every
-    directed CSR entry is one update) cut into insert batches of log-uniform
-    size in [1e4, 1e7], each request an insert batch or a batch of 1e5 uniform
-    query pairs with probability 1/2, until the edges run out."""
-    import numpy as np
-
+    """The incremental workload (graphgen.update_stream): RMAT at the serving
+    scale, both directions, insert batches of log-uniform size in [1e4, 1e7]
+    and query batches of 1e5 uniform pairs by coin flip."""
     import graphgen
-    sc = args.serve_scale
-    n = 1 << sc
-    src, dst = graphgen.rmat_edges(sc, args.edge_factor * n, args.seed + 100)
-    graphgen.shuffle_edges(src, dst, args.seed + 100)
-    E = len(src)
-    rng = np.random.default_rng(args.seed)
-    reqs, e = [], 0  # inserts: (0, lo, hi); queries: (1, a, b)
-    while e < 2 * E:
-        if rng.random() < 0.5:
-            k = int(10 ** rng.uniform(4, 7))
-            lo, hi = e, min(e + k, 2 * E)
-            if lo < E < hi:  # keep a batch inside one direction's pass
-                hi = E
-            reqs.append((0, lo, hi))
-            e = hi
-        else:
-            a, b = graphgen.uniform_pairs(n, 100_000, args.seed, len(reqs))
-            reqs.append((1, a, b))
-        if args.serve_requests and len(reqs) >= args.serve_requests:
-            break
-    return n, src, dst, reqs
+    return graphgen.update_stream(args.serve_scale, args.edge_factor, args.seed,
+                                  args.serve_requests)
 
 
 def insert_slices(src, dst, lo, hi):
-    """Updates lo..hi of the two-pass stream: (src, dst) first, then (dst, src)."""
-    E = len(src)
-    if lo >= E:
-        return dst[lo - E:hi - E], src[lo - E:hi - E]
-    return src[lo:hi], dst[lo:hi]
+    import graphgen
+    return graphgen.insert_slices(src, dst, lo, hi)
+
+
+def answers_sha16(ans) -> str:
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(ans, dtype=np.uint8).tobytes()).hexdigest()[:16]
+
+
+def stream_check(args, answers, labels=None, n=None) -> dict:
+    """Compare a replay of the update stream with the oracle's record of it
+    (tests/golden/make_golden.py): every query batch's answers by hash, in
+    request order, and -- when the whole stream ran and labels are given --
+    the final canonical labels and the number of components (distinct
+    labels).  A stream cut short by --serve-requests compares its prefix."""
+    import numpy as np
+    gold = golden(f"stream_rmat{args.serve_scale}_ef{args.edge_factor}_s{args.seed}")
+    if gold is None:
+        return {"answers_match_oracle": None, "labels_match_oracle": None}
+    want = gold["query_answers_sha16"]
+    got = [answers_sha16(a) for a in answers]
+    ok_ans = len(got) <= len(want) and got == want[:len(got)]
+    out = {"answers_match_oracle": bool(ok_ans), "query_batches_checked": len(got)}
+    if labels is not None and len(got) == len(want):
+        comps = int((labels == np.arange(n, dtype=np.uint32)).sum())
+        out["components"] = comps
+        out["components_match_oracle"] = comps == gold["components"]
+        out["labels_match_oracle"] = labels_sha(labels) == gold["labels_sha256"]
+    else:
+        out["labels_match_oracle"] = None
+    return out
 
 
 def incremental_bench(G, n, src, dst, reqs, args, rule=None) -> dict:
@@ -272,7 +346,10 @@ def incremental_bench(G, n, src, dst, reqs, args, rule=None) -> dict:
     d_d = torch.from_numpy(dst.view(np.int32)).to(dev)
     qs = [(torch.from_numpy(a.view(np.int32)).to(dev), torch.from_numpy(b.view(np.int32)).to(dev))
           for k, a, b in reqs if k == 1]
-    qout = torch.empty(100_000, dtype=torch.uint8, device=dev)
+    # every query batch answers into its own slice, checked after the timed run
+    qlen = [len(a) for a, _ in qs]
+    qoff = np.concatenate([[0], np.cumsum(qlen)]).astype(np.int64)
+    qall = torch.empty(max(int(qoff[-1]), 1), dtype=torch.uint8, device=dev)
     rule = rule or dict(link="async", find="split")
     inc = G.Incremental(n, options=G.Options(sample="none", **rule))
     torch.cuda.synchronize()
@@ -285,7 +362,7 @@ def incremental_bench(G, n, src, dst, reqs, args, rule=None) -> dict:
             a, b = insert_slices(s_d, d_d, x, y)
             inc.insert(a, b)
         else:
-            inc.query(qs[qi][0], qs[qi][1], out=qout)
+            inc.query(qs[qi][0], qs[qi][1], out=qall[int(qoff[qi]):int(qoff[qi + 1])])
             qi += 1
         e1.record()
         evs.append((k, e0, e1))
@@ -294,20 +371,12 @@ def incremental_bench(G, n, src, dst, reqs, args, rule=None) -> dict:
     lat_i = [a.elapsed_time(b) for k, a, b in evs if k == 0]
     lat_q = [a.elapsed_time(b) for k, a, b in evs if k == 1]
     updates = sum(y - x for k, x, y in reqs if k == 0)
-    # invariants of the final labels: every streamed edge inside one label,
-    # labels are minima (L[v] <= v) and fixed points (L[L[v]] == L[v])
-    lab = inc.labels().long()
-    last = max((y for k, x, y in reqs if k == 0), default=0)
-    m_in = min(last, len(src))
-    ok = True
-    for c0 in range(0, m_in, 1 << 27):
-        c1 = min(m_in, c0 + (1 << 27))
-        ok = ok and bool((lab[s_d[c0:c1].long()] == lab[d_d[c0:c1].long()]).all().item())
-    ok = ok and bool((lab <= torch.arange(n, device=dev)).all().item())
-    ok = ok and bool((lab[lab] == lab).all().item())
-    del lab
+    answers = qall.cpu().numpy()
+    lab = G.to_u32(inc.labels())
     inc.close()
-    del s_d, d_d, qs
+    del s_d, d_d, qs, qall
+    check = stream_check(args, [answers[qoff[i]:qoff[i + 1]] for i in range(len(qlen))], lab, n)
+    del lab
     return {"updates": updates, "insert_batches": len(lat_i), "query_batches": len(lat_q),
             "insert_updates_per_s": round(updates / (sum(lat_i) * 1e-3), 1),
             "stream_updates_per_s": round(updates / wall, 1),
@@ -315,7 +384,7 @@ def incremental_bench(G, n, src, dst, reqs, args, rule=None) -> dict:
             "insert_batch_ms_p99": round(percentile(lat_i, 99), 4),
             "query_batch_ms_p50": round(percentile(lat_q, 50), 4),
             "query_batch_ms_p99": round(percentile(lat_q, 99), 4),
-            "label_invariants_hold": ok}
+            **check}
 
 
 def serving_bench(G, n, src, dst, reqs, args) -> dict:
@@ -329,6 +398,7 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
     import torch
     rng = np.random.default_rng(args.seed)
     opts = G.Options(sample="none", link="async", find="split")
+    checks = []  # per run: every query batch's answers against the oracle's record
 
     def requests(s_arr, d_arr):
         return [(0,) + insert_slices(s_arr, d_arr, x, y) if k == 0 else (1, x, y)
@@ -348,10 +418,12 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
                 while time.perf_counter() < nxt:
                     pass
                 tickets.append(srv.submit(k, a, b))
-        recs = [srv.wait(t)[0] for t in tickets]
+        done = [srv.wait(t) for t in tickets]
         wall = time.perf_counter() - t0
         srv.close()
-        lat = [(r["done_us"] - r["submit_us"]) / 1e3 for r in recs]
+        lat = [(r["done_us"] - r["submit_us"]) / 1e3 for r, _ in done]
+        answers = [out for (r, out), (k, _, _) in zip(done, host) if k == 1]
+        checks.append(stream_check(args, answers)["answers_match_oracle"])
         return wall, lat
 
     def by_kind(host, lat):
@@ -404,6 +476,9 @@ def serving_bench(G, n, src, dst, reqs, args) -> dict:
     out["pinned_inputs"] = sweep(requests(ps.numpy().view(np.uint32),
                                           pd.numpy().view(np.uint32)))
     del ps, pd
+    out["runs_checked"] = len(checks)
+    out["answers_match_oracle"] = (None if any(c is None for c in checks)
+                                   else all(checks))
     return out
 
 
@@ -468,8 +543,25 @@ def batched_bench(G, args) -> dict:
     t_cap = (time.perf_counter() - t0) / reps
     ex.close()
     lb = lab_b.cpu().numpy().view(np.uint32)
-    same = all(np.array_equal(lb[int(hb.vbase[i]):int(hb.vbase[i]) + g.n], G.to_u32(l))
-               for i, (g, l) in enumerate(zip(graphs, labs)))
+    slices = [lb[int(hb.vbase[i]):int(hb.vbase[i]) + g.n] for i, g in enumerate(graphs)]
+    same = all(np.array_equal(sl, G.to_u32(l)) for sl, l in zip(slices, labs))
+    del labs, dgs, ws_1, ws_b, db, lab_b
+    # the oracle's record of the same batch (per-graph label hashes)
+    gold = golden(f"batch{args.batch_graphs}_s{args.seed}")
+    match_gold = None
+    if gold is not None and gold["n_range"][1] == args.batch_nmax:
+        match_gold = all(rec[0] == g.n and rec[1] == g.m and answers_sha16(sl.view(np.uint8)) ==
+                         rec[3] for rec, g, sl in zip(gold["per_graph"], graphs, slices))
+    # the oracle itself, graph-parallel on the host's cores: CPU baseline and a
+    # second check of every graph's labels
+    import oracle
+    workers = pool_size()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:  # the oracle releases the GIL
+        want = list(ex.map(lambda g: oracle.cc(g.n, g.offsets, g.nbrs), graphs))
+    t_cpu = time.perf_counter() - t0
+    match_run = all(np.array_equal(w, sl) for w, sl in zip(want, slices))
+    del want
     return {"workload": f"{len(graphs)} graphs, n log-uniform in [1e3, {args.batch_nmax:.0e}], "
                         "ER or RMAT by coin flip, edge factor 8..32",
             "graphs": len(graphs), "n": total_n, "m_directed": total_m,
@@ -480,7 +572,14 @@ def batched_bench(G, args) -> dict:
             "speedup": round(t_loop / t_batch, 2),
             "batched_gedges_per_s": round(total_m / t_batch / 1e9, 2),
             "per_graph_gedges_per_s": round(total_m / t_loop / 1e9, 2),
-            "labels_identical": bool(same)}
+            "labels_identical_to_per_graph_launches": bool(same),
+            "labels_match_oracle_golden": match_gold,
+            "labels_match_oracle": bool(match_run),
+            "cpu_baseline": {"value": round(total_m / t_cpu / 1e9, 4), "unit": "Gedges/s",
+                             "cores": workers, "kind": "oracle",
+                             "sample": f"all {len(graphs)} graphs, one oracle run each, "
+                                       f"graph-parallel on {workers} threads ({t_cpu:.1f} s)",
+                             "seconds": round(t_cpu, 2), **host_info()}}
 
 
 def other_configs_bench(G, args) -> dict:
@@ -620,7 +719,7 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--kout-prelink", type=int, default=0, choices=(0, 1))
     ap.add_argument("--kout-local", type=int, default=0, choices=(0, 1))
-    ap.add_argument("--schedule", default="auto", choices=("auto", "lane", "step", "pipe", "twopass"),
+    ap.add_argument("--schedule", default="auto", choices=("auto", "lane", "step", "pipe", "twopass", "flat"),
                     help="k-out kernel schedule (twopass: rows streamed to a slot array, then "
                          "the union pass over the slots)")
     ap.add_argument("--atomic-compress", type=int, default=1, choices=(0, 1))
@@ -757,6 +856,7 @@ def main() -> int:
         dom_ms = timed_sample_ms  # measured inside the timed region
     achieved = abytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
     total_alg = sum(abytes.values())
+    step_bytes = step_model_bytes(n, st)
     log(f"phases (ms): {json.dumps({k: round(v, 4) for k, v in phase_ms.items()})}")
 
     traffic = None
@@ -780,8 +880,13 @@ def main() -> int:
         "traffic_frac": round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         if traffic and dom_ms > 0 else None,
         "alg_bytes_per_launch": abytes[dominant], "launch_ms": round(dom_ms, 5),
-        "step_alg_bytes": total_alg,
-        "step_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the whole step against the bytes model 28n + 12(E_s + E_f) + 12A + 4H
+        "step_alg_bytes": step_bytes,
+        "step_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the same with the per-phase model above (finalisation over the active
+        # set only, no hook writes): what this pipeline's kernels must move
+        "step_alg_bytes_phase_model": total_alg,
+        "step_frac_phase_model": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
 
     result = {
@@ -887,10 +992,11 @@ def main() -> int:
                      dict(link="early", find="halve"), dict(link="hooks", find="split"),
                      dict(link="jtb", find="two_try_split")):
             r = incremental_bench(G, sn, ssrc, sdst, reqs, args, rule)
-            rules["+".join(rule.values())] = {k: r[k] for k in (
+            rules["+".join(rule.values())] = {k: r.get(k) for k in (
                 "insert_updates_per_s", "insert_batch_ms_p99", "query_batch_ms_p99",
-                "label_invariants_hold")}
+                "answers_match_oracle", "labels_match_oracle")}
         result["incremental"]["device_resident_rules"] = rules
+        result["incremental"]["cpu_baseline"] = incremental_cpu_baseline(sn, ssrc, sdst, reqs)
         log(f"incremental stream built in {time.time() - t0:.1f}s: {result['incremental']}")
         if not args.no_serving:
             result["incremental"]["host_fed_server"] = serving_bench(G, sn, ssrc, sdst, reqs, args)
@@ -914,6 +1020,7 @@ def main() -> int:
                       f"({t_cpu:.1f} s, generation excluded)",
             "seconds": round(t_cpu, 2),
             "labels_match_gpu": bool(np.array_equal(want, got)),
+            **host_info(),
         }
         log(f"cpu oracle {t_cpu:.2f}s match={result['cpu_baseline']['labels_match_gpu']}")
 

@@ -216,6 +216,48 @@ def uniform_pairs(n: int, q: int, seed: int, stream: int = 0):
 
 
 # ---------------------------------------------------------------- workloads
+def update_stream(scale: int, edge_factor: int, seed: int, max_requests: int = 0):
+    """The incremental serving workload: an RMAT edge stream (scale, edge
+    factor, stream seed seed + 100, shuffled) played in both directions, so
+    every directed CSR entry is one update, cut into requests: each request is
+    an insert batch of log-uniform size in [1e4, 1e7] (kept inside one
+    direction's pass) or a batch of 1e5 uniform query pairs, with probability
+    1/2 each (numpy's default_rng(seed)), until the updates run out or
+    max_requests (> 0) requests exist.
+
+    Returns (n, src, dst, reqs): inserts are (0, lo, hi), update indices of
+    the two-pass stream (see insert_slices); queries are (1, a, b)."""
+    n = 1 << scale
+    src, dst = rmat_edges(scale, edge_factor * n, seed + 100)
+    shuffle_edges(src, dst, seed + 100)
+    E = len(src)
+    rng = np.random.default_rng(seed)
+    reqs, e = [], 0
+    while e < 2 * E:
+        if rng.random() < 0.5:
+            k = int(10 ** rng.uniform(4, 7))
+            lo, hi = e, min(e + k, 2 * E)
+            if lo < E < hi:
+                hi = E
+            reqs.append((0, lo, hi))
+            e = hi
+        else:
+            a, b = uniform_pairs(n, 100_000, seed, len(reqs))
+            reqs.append((1, a, b))
+        if max_requests and len(reqs) >= max_requests:
+            break
+    return n, src, dst, reqs
+
+
+def insert_slices(src, dst, lo: int, hi: int):
+    """Updates lo..hi of the two-pass stream: (src, dst) first, then (dst, src).
+    Works on numpy arrays and on torch tensors alike (slicing only)."""
+    E = len(src)
+    if lo >= E:
+        return dst[lo - E:hi - E], src[lo - E:hi - E]
+    return src[lo:hi], dst[lo:hi]
+
+
 def er(n: int, m_draws: int, seed: int = 1) -> CSR:
     s, d = er_edges(n, m_draws, seed)
     return csr_from_edges(n, s, d, True, f"er_n{n}_m{m_draws}_s{seed}")
