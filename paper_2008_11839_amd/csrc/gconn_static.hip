@@ -396,6 +396,41 @@ __global__ void k_kout_residual(const uint2* __restrict__ res, uint32_t n, LinkC
   }
 }
 
+// Flattening of the pre-link forest (the flat k-out schedule): every vertex
+// is pointed straight at its tree's root before the residual unions run, so
+// those start from roots instead of walking the pre-link chains once per
+// union.  No link runs in this pass and every write stores a root that is an
+// ancestor of the slot's vertex, so reads may be cached and stale; the writes
+// are agent-scope stores (two waves can share a line of P).
+__global__ void k_flatten(uint32_t* P, uint32_t n) {
+  for (uint64_t v = gtid(); v < n; v += wave_stride()) {
+    const uint32_t p = ld(&P[v]);
+    if (p == v) continue;
+    uint32_t r = p, q = ld(&P[p]);
+    while (q != r) {
+      r = q;
+      q = ld(&P[r]);
+    }
+    if (r != p) st(&P[v], r);
+  }
+}
+
+// Residual union pass of the flat schedule: both endpoints' parents are loaded
+// together before the unions run (a parent value the slot has held is a valid
+// start for the root-based rules; the splice rule re-reads them itself).
+template <class R>
+__global__ void k_kout_residual_flat(const uint2* __restrict__ res, uint32_t n, LinkCtx lc) {
+  for (uint64_t v = gtid(); v < n; v += wave_stride()) {
+    const uint2 r = res[v];
+    if (r.x == kEmpty) continue;  // r.y is empty too
+    const uint32_t pv = ld(&lc.P[v]);
+    const uint32_t p0 = ld(&lc.P[r.x]);
+    const uint32_t p1 = r.y != kEmpty ? ld(&lc.P[r.y]) : kEmpty;
+    R::unite_from(lc, (uint32_t)v, r.x, pv, p0);
+    if (r.y != kEmpty) R::unite_from(lc, (uint32_t)v, r.y, pv, p1);
+  }
+}
+
 // The same first-k sampling with Union-Rem-CAS as a lane-refill step machine
 // (uint32 offsets).  Each iteration: pick at most two addresses from the
 // lane's state, load them together, decide, issue at most one CAS, update the
@@ -1327,9 +1362,13 @@ bool kout_local_applies(const gconn_options& o) {
   return (o.kout_local || o.schedule == 4) && o.sample == GCONN_SAMPLE_KOUT && !o.kout_random &&
          o.k <= 2;
 }
-bool kout_prelink_applies(const gconn_options& o) {
-  return !kout_local_applies(o) && o.kout_prelink && o.sample == GCONN_SAMPLE_KOUT &&
+bool kout_flat_applies(const gconn_options& o) {
+  return !kout_local_applies(o) && o.schedule == 5 && o.sample == GCONN_SAMPLE_KOUT &&
          !o.kout_random && o.k <= 2;
+}
+bool kout_prelink_applies(const gconn_options& o) {
+  return !kout_local_applies(o) && (o.kout_prelink || kout_flat_applies(o)) &&
+         o.sample == GCONN_SAMPLE_KOUT && !o.kout_random && o.k <= 2;
 }
 
 template <class Fn>
@@ -1507,6 +1546,20 @@ struct Run {
           using R = decltype(rule);
           k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n, link_ctx());
           GCONN_LAUNCHED("k_kout_residual");
+          return GCONN_OK;
+        }));
+      } else if (kout_flat_applies(o)) {
+        uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
+        const uint32_t pgrid = std::min<uint32_t>(gridN(n), 8192);
+        k_kout_prelink<OffT><<<pgrid, block, 0, s>>>(off, g.nbrs, n, o.k, P, res, fu, fv, st);
+        GCONN_LAUNCHED("k_kout_prelink");
+        k_flatten<<<std::min<uint32_t>(gridN(n), 8192), block, 0, s>>>(P, n);
+        GCONN_LAUNCHED("k_flatten");
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          k_kout_residual_flat<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n,
+                                                                                  link_ctx());
+          GCONN_LAUNCHED("k_kout_residual_flat");
           return GCONN_OK;
         }));
       } else if (kout_prelink_applies(o)) {

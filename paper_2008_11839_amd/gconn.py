@@ -23,7 +23,7 @@ LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt
         "afforest": 8, "rem_lock": 9, "jtb": 10}
 FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3, "two_try_split": 4}
 SPLICE = {"split_one": 0, "halve_one": 1, "splice_atomic": 2}
-SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3, "twopass": 4}
+SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3, "twopass": 4, "flat": 5}
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
                "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]
 STATUS = {0: "GCONN_OK", -1: "GCONN_EINVAL", -2: "GCONN_ENOMEM", -3: "GCONN_EDEVICE",
