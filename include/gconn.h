@@ -216,6 +216,25 @@ gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspac
                       size_t workspace_bytes, const gconn_options* opt, gconn_stats* stats,
                       void* stream);
 
+/* gconn_cc without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that must not call
+ * hipMalloc, harnesses that forbid it).  Same arguments and results as
+ * gconn_cc minus the workspace: the pipeline runs in a scratch array of
+ * GCONN_NOALLOC_SCRATCH_BYTES that the library holds in device memory, one per
+ * device, from the first use until the process ends.  The call allocates
+ * nothing (no hipMalloc, no hipFree, no allocating library routine).
+ * Returns GCONN_ENOMEM, before enqueuing anything, when gconn_workspace_size
+ * for this graph and these options exceeds the scratch size (about n <= 7.5M
+ * vertices for the default k-out pipeline), and GCONN_EUNSUPPORTED while phase
+ * profiling is on.  Every call on one device shares that device's scratch
+ * array and leaves it holding its own intermediate state (each run clears what
+ * it needs with kernels): calls that may overlap on one device -- on
+ * different streams, or from different threads -- race and must be
+ * serialised by the caller. */
+#define GCONN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gconn_status gconn_cc_noalloc(const gconn_graph* g, uint32_t* labels_out,
+                              const gconn_options* opt, gconn_stats* stats, void* stream);
+
 /* Spanning forest (Alg. "GConn for Spanning Forest"): for every vertex r that
  * stops being a root, fu[r], fv[r] (device, n entries each) receive the input
  * edge that linked it; other slots hold 0xFFFFFFFF.  Exactly n - c slots are

@@ -148,6 +148,40 @@ static gconn_status check_workspace(void* ws, size_t have, size_t need) {
 
 using namespace gconn;
 
+// Scratch memory of gconn_cc_noalloc: a file-scope device array, so that the
+// call needs no allocation.  Each device the library runs on holds its own
+// copy (GCONN_NOALLOC_SCRATCH_BYTES) until the process ends.  In host code the
+// array's name is only a host-side stand-in: its device address is taken once
+// per device with hipGetSymbolAddress and only that address reaches kernels.
+static __device__ __align__(256) uint8_t scratch[GCONN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call made with that device current).
+gconn_status scratch_on_current_device(uint8_t** out) {
+  int dev = -1;
+  GCONN_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(GCONN_ENODEV, "device index " + std::to_string(dev) + " out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    GCONN_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0)
+      return fail(GCONN_EDEVICE, "scratch array has no 256-byte aligned device address");
+    g_scratch_dev[dev] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return GCONN_OK;
+}
+
+}  // namespace
+
 struct gconn_inc {
   uint32_t n_max;
   uint32_t* P;
@@ -256,6 +290,31 @@ gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspac
   GCONN_TRY(check_workspace(workspace, workspace_bytes, L.total));
   return run_static(*g, labels_out, nullptr, nullptr, true, static_cast<uint8_t*>(workspace), L, o,
                     stats, static_cast<hipStream_t>(stream));
+}
+
+gconn_status gconn_cc_noalloc(const gconn_graph* g, uint32_t* labels_out,
+                              const gconn_options* opt, gconn_stats* stats, void* stream) {
+  clear_error();
+  gconn_options o;
+  GCONN_TRY(resolve_options(opt, &o));
+  // Phase profiling creates HIP events on first use; this entry point makes
+  // no such call.
+  if (gconn::profiling())
+    return fail(GCONN_EUNSUPPORTED, "phase profiling is on: gconn_cc_noalloc does not time phases");
+  GCONN_TRY(check_device_ready());
+  GCONN_TRY(check_graph(g));
+  if (g->format == GCONN_COO) o.sample = GCONN_SAMPLE_NONE;
+  if (g->n > 0) GCONN_TRY(check_device_ptr(labels_out, "labels_out"));
+  const WsLayout L = plan_workspace(*g, o, false, true);
+  if (L.total > GCONN_NOALLOC_SCRATCH_BYTES)
+    return fail(GCONN_ENOMEM, "graph and options need " + std::to_string(L.total) +
+                                  " bytes of scratch; gconn_cc_noalloc has " +
+                                  std::to_string((size_t)GCONN_NOALLOC_SCRATCH_BYTES) +
+                                  " (use gconn_cc with a workspace)");
+  uint8_t* ws = nullptr;
+  GCONN_TRY(scratch_on_current_device(&ws));
+  return run_static(*g, labels_out, nullptr, nullptr, true, ws, L, o, stats,
+                    static_cast<hipStream_t>(stream));
 }
 
 gconn_status gconn_spanning_forest(const gconn_graph* g, uint32_t* fu, uint32_t* fv,

@@ -93,7 +93,7 @@ class _PhaseTimes(ctypes.Structure):
 
 EXPORTS = ["gconn_server_create", "gconn_server_submit", "gconn_server_wait",
            "gconn_server_drain", "gconn_server_destroy", "gconn_cc_batch_workspace_size", "gconn_cc_batch", "gconn_autotune",
-           "gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_spanning_forest",
+           "gconn_profile_enable", "gconn_profile_read", "gconn_options_default", "gconn_workspace_size", "gconn_cc", "gconn_cc_noalloc", "gconn_spanning_forest",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
            "gconn_inc_query_batch", "gconn_inc_mixed_batch", "gconn_inc_labels", "gconn_inc_destroy",
            "gconn_cc_capture", "gconn_cc_batch_capture", "gconn_exec_launch", "gconn_exec_destroy",
@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
         L.gconn_workspace_size.argtypes = [gp, op, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)]
         L.gconn_cc.restype = ctypes.c_int
         L.gconn_cc.argtypes = [gp, vp, vp, sz, op, stp, vp]
+        L.gconn_cc_noalloc.restype = ctypes.c_int
+        L.gconn_cc_noalloc.argtypes = [gp, vp, op, stp, vp]
         L.gconn_spanning_forest.restype = ctypes.c_int
         L.gconn_spanning_forest.argtypes = [gp, vp, vp, vp, vp, sz, op, stp, vp]
         L.gconn_inc_workspace_size.restype = ctypes.c_int
@@ -321,6 +323,22 @@ def cc(g: DeviceGraph, labels: torch.Tensor | None = None, options: Options | No
     _check(lib().gconn_cc(ctypes.byref(g.c), _ptr(labels) if g.n else None, workspace.data_ptr(),
                           workspace.numel(), ctypes.byref(o), ctypes.byref(st) if st else None,
                           _stream(stream)))
+    return (labels, _stats_dict(st)) if stats else labels
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # GCONN_NOALLOC_SCRATCH_BYTES
+
+
+def cc_noalloc(g: DeviceGraph, labels: torch.Tensor, options: Options | None = None,
+               stats: bool = False, stream=None):
+    """gconn_cc_noalloc: gconn_cc without a workspace (the library's own
+    per-device scratch array; raises GconnError with GCONN_ENOMEM when the
+    graph needs more than NOALLOC_SCRATCH_BYTES)."""
+    o = (options or Options()).to_c()
+    st = _Stats() if stats else None
+    _check(lib().gconn_cc_noalloc(ctypes.byref(g.c), _ptr(labels) if g.n else None,
+                                  ctypes.byref(o), ctypes.byref(st) if st else None,
+                                  _stream(stream)))
     return (labels, _stats_dict(st)) if stats else labels
 
 
