@@ -45,6 +45,8 @@ def sample_kernels(args) -> str:
         return "k_kout_local+k_kout_residual"
     if args.schedule == "flat":
         return "k_kout_prelink+k_flatten+k_kout_residual_flat"
+    if args.schedule == "xcd":
+        return "k_kx_stream+k_kx_flatten+k_kx_unite"
     if args.kout_prelink:
         return "k_kout_prelink+k_kout_residual"
     return {"auto": "k_sample_kout_pf", "lane": "k_sample_kout", "pipe": "k_sample_kout_pipe",
@@ -72,7 +74,7 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
+def algorithmic_bytes(n: int, m: int, st: dict, samples: int, init_in_sample: bool = False) -> dict:
     """Bytes each phase must move at 4-byte granularity (uint32 ids and labels).
 
     init: write P (4n).  sample (k-out): read offsets (4(n+1)) and, per sampled
@@ -83,6 +85,10 @@ def algorithmic_bytes(n: int, m: int, st: dict, samples: int) -> dict:
     after sampling): read the list, read + write P (12A).
     """
     Es, A, Ef = st["sampled_edges"], st["active_vertices"], st["finish_edges"]
+    if init_in_sample:  # the XCD-bucketed k-out writes every parent itself
+        return {"init_ms": 0, "sample_ms": 4 * n + 4 * (n + 1) + 12 * Es, "lmax_ms": 4 * samples,
+                "gather_ms": 12 * n + 4 + 4 * A, "finish_ms": 8 * A + 12 * Ef,
+                "finalize_ms": 12 * A}
     return {"init_ms": 4 * n, "sample_ms": 4 * (n + 1) + 12 * Es, "lmax_ms": 4 * samples,
             "gather_ms": 12 * n + 4 + 4 * A, "finish_ms": 8 * A + 12 * Ef,
             "finalize_ms": 12 * A}
@@ -582,6 +588,38 @@ def batched_bench(G, args) -> dict:
                              "seconds": round(t_cpu, 2), **host_info()}}
 
 
+def ceilings_bench(G, args) -> dict:
+    """The chip's random-access ceilings on a 64 MB table (the size of the
+    RMAT-24 parent array): random 4-byte cached loads, device-coherent loads
+    and CAS per second (gconn_diag_random_access, HIP events on the launch
+    stream, median of 5 after a warm-up)."""
+    import numpy as np
+    import torch
+    words = 1 << 24
+    table = torch.arange(words, dtype=torch.int32, device="cuda")
+    sink = torch.empty(256 * 2048, dtype=torch.int32, device="cuda")
+    accesses = 1 << 26
+    out = {"table_bytes": 4 * words, "accesses_per_launch": accesses}
+    stream = torch.cuda.current_stream()
+    for kind, name in ((0, "load_cached"), (1, "load_coherent"), (2, "cas")):
+        G.diag_random_access(table, kind, accesses, sink)
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            G.diag_random_access(table, kind, accesses, sink)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        # the kernel rounds the count down to whole steps of 8 per lane
+        done = accesses // (sink.numel() * 8) * sink.numel() * 8
+        out[name + "_per_s"] = round(done / (ms * 1e-3), 1)
+    assert bool((table == torch.arange(words, dtype=torch.int32, device="cuda")).all())
+    del table, sink
+    return out
+
+
 def other_configs_bench(G, args) -> dict:
     """The other static workloads: ER (n = 1e5, 1e6 draws: a latency / launch
     overhead case) and the bond-percolation grids (2D 4096^2 at p = 0.7, 3D
@@ -719,7 +757,7 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--kout-prelink", type=int, default=0, choices=(0, 1))
     ap.add_argument("--kout-local", type=int, default=0, choices=(0, 1))
-    ap.add_argument("--schedule", default="auto", choices=("auto", "lane", "step", "pipe", "twopass", "flat"),
+    ap.add_argument("--schedule", default="auto", choices=("auto", "lane", "step", "pipe", "twopass", "flat", "xcd"),
                     help="k-out kernel schedule (twopass: rows streamed to a slot array, then "
                          "the union pass over the slots)")
     ap.add_argument("--atomic-compress", type=int, default=1, choices=(0, 1))
@@ -847,7 +885,10 @@ def main() -> int:
     G.profile_enable(False)
     runs = max(ph.pop("runs"), 1)
     phase_ms = {k: v / runs for k, v in ph.items() if k in PHASE_KERNEL}
-    abytes = algorithmic_bytes(n, m, st, opts.lmax_samples)
+    abytes = algorithmic_bytes(n, m, st, opts.lmax_samples,
+                               init_in_sample=args.sample == "kout" and args.schedule == "xcd")
+    if args.sample == "kout" and args.schedule == "xcd":
+        PHASE_KERNEL["init_ms"] = "k_ctrl_init"
     if args.sample == "kout":
         PHASE_KERNEL["sample_ms"] = sample_kernels(args)
     dominant = max(phase_ms, key=lambda k: phase_ms[k])
@@ -888,6 +929,21 @@ def main() -> int:
         "step_alg_bytes_phase_model": total_alg,
         "step_frac_phase_model": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
+
+    # the union passes against the chip's random-access ceilings: the bytes
+    # model's two parent reads per sampled entry, and one CAS per hook
+    ceil = ceilings_bench(G, args)
+    if dominant == "sample_ms" and dom_ms > 0:
+        reads_per_s = 2 * st["sampled_edges"] / (dom_ms * 1e-3)
+        cas_per_s = st["hooks"] / (dom_ms * 1e-3)
+        ceil["sample_phase"] = {
+            "model_parent_reads": 2 * st["sampled_edges"], "hooks": st["hooks"],
+            "parent_reads_per_s": round(reads_per_s, 1),
+            "frac_of_cached_load_ceiling": round(reads_per_s / ceil["load_cached_per_s"], 4),
+            "frac_of_coherent_load_ceiling": round(reads_per_s / ceil["load_coherent_per_s"], 4),
+            "frac_of_cas_ceiling": round(cas_per_s / ceil["cas_per_s"], 4)}
+    roofline["random_access"] = ceil
+    log(f"random-access ceilings {ceil}")
 
     result = {
         "metric": METRIC, "value": round(value, 2), "unit": "Gedges/s", "n_gpus": 1,

@@ -450,6 +450,20 @@ gconn_status gconn_profile_enable(int on);
 /* Fills *out with the totals since the last reset; reset = 1 clears them. */
 gconn_status gconn_profile_read(gconn_phase_times* out, int reset);
 
+/* Diagnostics: the chip's random-access ceilings, the yardstick of the union
+ * passes (whose cost is the number of data-dependent 4-byte parent reads and
+ * CASes the memory system serves per second, not streaming bandwidth).
+ * Enqueues one kernel on `stream` that makes `accesses` (rounded down to a
+ * multiple of 8 * lanes) random 4-byte accesses to table[0, words): kind 0
+ * cached loads, 1 device-coherent loads, 2 CAS of each word's value to
+ * itself (the table must hold table[i] == i, and is left unchanged).
+ * sink (device, sink_words >= 256 entries) receives one word per lane;
+ * lanes = sink_words rounded down to a multiple of 256.  words must be a power of
+ * two.  Time it with events on the same stream. */
+gconn_status gconn_diag_random_access(uint32_t* table, uint64_t words, int kind,
+                                      uint64_t accesses, uint32_t* sink, uint32_t sink_words,
+                                      void* stream);
+
 const char* gconn_status_string(gconn_status s);
 /* Message for the most recent failure on the calling thread ("" if none). */
 const char* gconn_last_error(void);

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgconn.so")
 OBJDIR = os.path.join(ROOT, "_build", "gconn")
 SOURCES = ["gconn_static.hip", "gconn_jtb.hip", "gconn_batch.hip", "gconn_server.hip",
-           "gconn_api.hip"]
+           "gconn_api.hip", "gconn_diag.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -60,7 +60,7 @@ gconn_status check_options(const gconn_options& o) {
   if (o.hb_n < 1 || o.hb_n > 1024) return fail(GCONN_EINVAL, "options.hb_n must be in [1, 1024]");
   if (o.lmax_samples < 1 || o.lmax_samples > kMaxLmaxSamples)
     return fail(GCONN_EINVAL, "options.lmax_samples must be in [1, 4096]");
-  if (o.schedule < 0 || o.schedule > 5) return fail(GCONN_EINVAL, "options.schedule out of range");
+  if (o.schedule < 0 || o.schedule > 6) return fail(GCONN_EINVAL, "options.schedule out of range");
   if (o.atomic_compress != 0 && o.atomic_compress != 1)
     return fail(GCONN_EINVAL, "options.atomic_compress must be 0 or 1");
   if (o.kout_prelink != 0 && o.kout_prelink != 1)

@@ -50,6 +50,12 @@ struct Ctrl {
   uint32_t small_cnt[kSubLists];
   uint32_t medium_cnt[kSubLists];
   uint32_t changed[kRoundSlots];
+  uint32_t kx_queue[8];               // XCD-bucketed k-out: per-XCD work-item cursors
+  // BFS sampling, decided on the device level by level
+  uint32_t bfs_mode;                  // this level: 0 finished, 1 top-down, 2 bottom-up
+  uint32_t bfs_convert;               // 1: queue -> bitmap first, 2: bitmap -> queue first
+  uint32_t bfs_as_queue;              // the current frontier is held as a queue
+  uint32_t bfs_levels;                // levels run
 };
 
 struct WsLayout {
@@ -69,6 +75,10 @@ struct WsLayout {
   size_t words = 0;   // Union-JTB (rank, parent) words (uint64[n])
   size_t roots = 0;   // Union-JTB flat roots after sampling (uint32[n])
   size_t mins = 0;    // Union-JTB component minima for the labels (uint32[n])
+  size_t kx_src = 0;  // XCD-bucketed k-out: residual records, first endpoint (uint32[chunks][2048])
+  size_t kx_dst = 0;  //   second endpoint (same layout)
+  size_t kx_root = 0; //   root of the first endpoint's pre-link tree (same layout)
+  size_t kx_hdr = 0;  //   records per (chunk, XCD group) (uint32[chunks][8])
   uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;

@@ -85,6 +85,9 @@ enum UnionRule : int {
 #ifndef GCONN_P_LOAD_SCOPE
 #define GCONN_P_LOAD_SCOPE __HIP_MEMORY_SCOPE_WAVEFRONT
 #endif
+#ifndef GCONN_ROOT_RECHECK
+#define GCONN_ROOT_RECHECK 0
+#endif
 
 // Read of P inside a find / union loop (see the memory-model note above).  A
 // host build may route it through GCONN_HOST_STALE_LOAD(p), a function that
@@ -297,9 +300,11 @@ GCONN_HD bool union_early(const LinkCtx& c, uint32_t u, uint32_t v) {
 // that validates r_u is still a root.
 template <int F, int S>
 GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu = kEmpty,
-                            uint32_t pv = kEmpty) {
+                            uint32_t pv = kEmpty, uint32_t eu = kEmpty, uint32_t ev = kEmpty) {
   // pu, pv: values P[u], P[v] are known to have held (a caller that loaded
-  // them ahead of time); kEmpty reads them here.
+  // them ahead of time); kEmpty reads them here.  eu, ev: the input edge a
+  // spanning forest records for a link (kEmpty: (u, v) itself) -- a caller
+  // may unite an ancestor u of eu instead of eu, which joins the same sets.
   uint32_t ru = u, rv = v;
   uint32_t pru = pu != kEmpty ? pu : ld(&c.P[ru]), prv = pv != kEmpty ? pv : ld(&c.P[rv]);
   for (;;) {
@@ -313,9 +318,18 @@ GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t p
       prv = t;
     }
     if (ru == pru) {
+#if GCONN_ROOT_RECHECK
+      {
+        const uint32_t fresh = ld_agent(&c.P[ru]);
+        if (fresh != ru) {
+          pru = fresh;
+          continue;
+        }
+      }
+#endif
       uint32_t e = ru;
       if (cas(&c.P[ru], e, prv)) {
-        record_link(c, ru, u, v);
+        record_link(c, ru, eu != kEmpty ? eu : u, ev != kEmpty ? ev : v);
         if constexpr (F != kFindNaive) {
           // P[ru] is now prv, and prv was read as P[rv]: an endpoint that is
           // ru or rv starts its compressing find from prv.
@@ -349,11 +363,21 @@ GCONN_HD bool union_rem_cas(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t p
 // path, so the carried-value shortcuts of union_rem_cas do not apply: both
 // parents are re-read, device-coherently, on every iteration, and a failed
 // CAS only means the next iteration sees the new parent.
+// pu, pv (kEmpty: none): values P[u], P[v] held at some time, read without
+// coherence (an L2 copy may be stale); the first iteration compares them
+// instead of fresh reads.  Every value P[x] ever holds lies in the set x
+// belongs to once the phase's unions are done (each write stores an id of
+// the union's other side, and that union goes on to join the two sides), so
+// comparing a stale value unites sets that end up joined anyway, and a stale
+// "root" only costs one CAS that fails, after which the reads are coherent.
 template <int F>
-GCONN_HD bool union_rem_splice(const LinkCtx& c, uint32_t u, uint32_t v) {
+GCONN_HD bool union_rem_splice(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu = kEmpty,
+                               uint32_t pv = kEmpty) {
   uint32_t ru = u, rv = v;
   for (;;) {
-    uint32_t pru = ld_agent(&c.P[ru]), prv = ld_agent(&c.P[rv]);
+    uint32_t pru = pu != kEmpty ? pu : ld_agent(&c.P[ru]);
+    uint32_t prv = pv != kEmpty ? pv : ld_agent(&c.P[rv]);
+    pu = pv = kEmpty;
     if (pru == prv) return false;
     if (pru < prv) {
       uint32_t t = ru;
@@ -484,7 +508,19 @@ struct Rule {
   GCONN_HD static bool unite_from(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu,
                                   uint32_t pv) {
     if constexpr (U == kUnionRemCas && S != kSpliceAtomic) return union_rem_cas<F, S>(c, u, v, pu, pv);
+    else if constexpr (U == kUnionRemCas) return union_rem_splice<F>(c, u, v, pu, pv);
     else return unite(c, u, v);
+  }
+  // The union of the input edge (eu, v), started from u, an ancestor of eu
+  // (same set), with parent values pu, pv loaded ahead of time as above.  A
+  // spanning forest records (eu, v).  Union-Rem-CAS with SplitAtomicOne /
+  // HalveAtomicOne starts from u; the other rules unite (u, v) when no forest
+  // is recorded and (eu, v) when one is.
+  GCONN_HD static bool unite_edge(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu,
+                                  uint32_t pv, uint32_t eu) {
+    if constexpr (U == kUnionRemCas && S != kSpliceAtomic)
+      return union_rem_cas<F, S>(c, u, v, pu, pv, eu, v);
+    else return unite(c, c.fu ? eu : u, v);
   }
 };
 

@@ -29,6 +29,10 @@
 
 namespace gconn {
 
+#ifndef GCONN_PF_PREFETCH_P
+#define GCONN_PF_PREFETCH_P 0
+#endif
+
 // --------------------------------------------------------------- setup
 // P[v] = v and empty forest slots, four vertices per lane with 16-byte stores;
 // block 0 also clears the control block.
@@ -174,8 +178,19 @@ __global__ void k_sample_kout_pf(const OffT* __restrict__ off, const uint32_t* _
     fetch(nv, nb, nd, n0, n1);
     if (d > 0) {
       const uint32_t take = random ? k : (uint32_t)(d < k ? d : k);
-      R::unite(lc, (uint32_t)v, w0);
-      if (take > 1) R::unite(lc, (uint32_t)v, w1);
+#if GCONN_PF_PREFETCH_P
+      if constexpr (R::kUnion == kUnionRemCas) {
+        // both neighbours' parents in flight together, from the L2 when cached
+        const uint32_t p0 = ld(&lc.P[w0]);
+        const uint32_t p1 = take > 1 ? ld(&lc.P[w1]) : kEmpty;
+        R::unite_from(lc, (uint32_t)v, w0, kEmpty, p0);
+        if (take > 1) R::unite_from(lc, (uint32_t)v, w1, kEmpty, p1);
+      } else
+#endif
+      {
+        R::unite(lc, (uint32_t)v, w0);
+        if (take > 1) R::unite(lc, (uint32_t)v, w1);
+      }
       for (uint32_t j = 2; j < take; ++j) {
         uint64_t pick = j;
         if (random) pick = ((uint64_t)(uint32_t)(splitmix64_at(seed, v * k + j) >> 32) * d) >> 32;
@@ -305,7 +320,7 @@ __global__ void k_kout_prelink(const OffT* __restrict__ off, const uint32_t* __r
 }
 
 // Local-first k-out (first k <= 2 edges).  Workgroup r owns the id range
-// [r * kLocalRange, (r + 1) * kLocalRange): it unites the sampled edges with
+// [r * range, (r + 1) * range): it unites the sampled edges with
 // both endpoints in the range on a copy of the range's parents in LDS (LDS
 // atomics: far cheaper than device atomics, and the range's trees never
 // leave the CU), linking the larger local root under the smaller, so each
@@ -314,8 +329,15 @@ __global__ void k_kout_prelink(const OffT* __restrict__ off, const uint32_t* __r
 // leave the range to res[v] for the union pass.  Runs on a freshly
 // initialised P; the partition after both passes is the sampled one.  With
 // local == 0 it only streams the rows: every sampled edge goes to res[v] and
-// the union pass does all the linking (the two-pass schedule).
-constexpr uint32_t kLocalRange = 8192;
+// the union pass does all the linking (the two-pass schedule).  The range
+// is a power of two chosen at launch: the largest the device's LDS per
+// workgroup holds (4 bytes per vertex), up to kLocalRangeMax -- the wider it
+// is, the fewer sampled edges of a mesh-like graph leave it.
+#ifndef GCONN_LOCAL_RANGE_MAX
+#define GCONN_LOCAL_RANGE_MAX 32768
+#endif
+constexpr uint32_t kLocalRangeMax = GCONN_LOCAL_RANGE_MAX;
+constexpr uint32_t kLocalRangeMin = 8192;
 
 __device__ __forceinline__ uint32_t lds_root(uint32_t* L, uint32_t x) {
   for (;;) {
@@ -326,14 +348,14 @@ __device__ __forceinline__ uint32_t lds_root(uint32_t* L, uint32_t x) {
 }
 
 template <typename OffT>
-__global__ void __launch_bounds__(512) k_kout_local(const OffT* __restrict__ off,
-                                                    const uint32_t* __restrict__ nbrs,
-                                                    uint32_t n, uint32_t k, uint32_t* P, uint2* res,
-                                                    uint32_t* fu, uint32_t* fv, int local,
-                                                    Ctrl* stats) {
-  __shared__ uint32_t L[kLocalRange];
-  const uint64_t lo = (uint64_t)blockIdx.x * kLocalRange;
-  const uint32_t len = (uint32_t)min<uint64_t>(kLocalRange, n - lo);
+__global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ off,
+                                                     const uint32_t* __restrict__ nbrs,
+                                                     uint32_t n, uint32_t k, uint32_t range,
+                                                     uint32_t* P, uint2* res, uint32_t* fu,
+                                                     uint32_t* fv, int local, Ctrl* stats) {
+  extern __shared__ uint32_t L[];  // range entries
+  const uint64_t lo = (uint64_t)blockIdx.x * range;
+  const uint32_t len = (uint32_t)min<uint64_t>(range, n - lo);
   for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) L[i] = i;
   __syncthreads();
   unsigned long long sampled = 0, linked = 0;
@@ -428,6 +450,287 @@ __global__ void k_kout_residual_flat(const uint2* __restrict__ res, uint32_t n, 
     const uint32_t p1 = r.y != kEmpty ? ld(&lc.P[r.y]) : kEmpty;
     R::unite_from(lc, (uint32_t)v, r.x, pv, p0);
     if (r.y != kEmpty) R::unite_from(lc, (uint32_t)v, r.y, pv, p1);
+  }
+}
+
+// --------------------------------------------------------------- XCD-bucketed k-out
+// First-k k-out (k <= 2) arranged so that the union pass's parent reads stay
+// in the L2 of the XCD that makes them.  An MI355X has eight XCDs, each with
+// a private 4 MB L2, and a parent read that misses it costs a 128-byte line
+// across the fabric.  Three kernels:
+//  * k_kx_stream: one workgroup per 1024-vertex chunk reads the rows' first k
+//    neighbours and writes P[v] -- the pre-link of v under its smallest
+//    sampled neighbour when that is smaller (v is a root and this lane its
+//    only writer, so a plain store), else v itself -- and v's forest slots.
+//    The other sampled edges of the chunk ("residual", at most two per
+//    vertex) go to the chunk's record block, sorted into eight groups by the
+//    XCD that will unite them: edge (v, w) goes to group (w >> shift) & 7, so
+//    each XCD reads the parents of one eighth of the ids (interleaved ranges
+//    of 2^shift vertices, which spreads the low-id skew of sorted rows).
+//  * k_kx_flatten: per chunk, every vertex is pointed at its pre-link root,
+//    and every record's first endpoint is replaced by that root (the original
+//    endpoint is kept aside for spanning forests).
+//  * k_kx_unite: a persistent grid.  Each workgroup reads the id of the XCD
+//    it runs on and takes work items (kKxItem chunks' records of one group)
+//    from that XCD's queue, then from the others once it is empty, and unites
+//    each record with the configured rule.
+// The partition after the three passes is that of the sampled edge set.
+constexpr uint32_t kKxChunk = 1024;         // vertices per chunk: 256 lanes x 4
+constexpr uint32_t kKxCap = 2 * kKxChunk;   // residual records per chunk
+constexpr uint32_t kKxGroups = 8;           // record groups: one per XCD
+constexpr uint32_t kKxItem = 16;            // chunks per work item of the union pass
+
+// Id of the XCD running the calling wave (hardware register XCC_ID, id 20 on
+// gfx940 and later, bits [3:0]), folded into [0, 8).
+__device__ __forceinline__ uint32_t xcc_id() {
+  return (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kKxGroups - 1);
+}
+
+template <typename OffT>
+__global__ void __launch_bounds__(256) k_kx_stream(const OffT* __restrict__ off,
+                                                   const uint32_t* __restrict__ nbrs, uint32_t n,
+                                                   uint32_t k, uint32_t shift, uint32_t* P,
+                                                   uint32_t* fu, uint32_t* fv, uint32_t* rsrc,
+                                                   uint32_t* rdst, uint32_t* hdr, int vec,
+                                                   Ctrl* stats) {
+  // vec: bit 0 -- P, fu, fv are 16-byte aligned; bit 1 -- uint32 offsets are
+  __shared__ uint32_t cnt[kKxGroups], pos[kKxGroups + 1];
+  __shared__ uint32_t s_src[kKxCap], s_dst[kKxCap];
+  const uint64_t base = (uint64_t)blockIdx.x * kKxChunk;
+  if (threadIdx.x < kKxGroups) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t v0 = base + 4ull * threadIdx.x;
+  // row starts of the lane's four vertices (and the end of the last)
+  uint64_t o[5];
+  if ((vec & 2) && v0 + 4 <= n && sizeof(OffT) == 4) {
+    const uint4 a = *reinterpret_cast<const uint4*>(off + v0);
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    o[4] = off[v0 + 4];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] = v0 + j <= n ? (uint64_t)off[v0 + j] : 0;
+  }
+  uint32_t w0[4], w1[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint64_t d = v0 + j < n ? o[j + 1] - o[j] : 0;
+    w0[j] = d > 0 ? nbrs[o[j]] : kEmpty;
+    w1[j] = (d > 1 && k > 1) ? nbrs[o[j] + 1] : kEmpty;
+  }
+  uint32_t par[4], lo_[4], rec[8], slot[8];
+  unsigned long long sampled = 0, linked = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t v = (uint32_t)(v0 + j);
+    const uint64_t d = v0 + j < n ? o[j + 1] - o[j] : 0;
+    sampled += d < k ? d : k;
+    const uint32_t a = w0[j] == v ? kEmpty : w0[j];
+    const uint32_t c = (w1[j] == v || w1[j] == a) ? kEmpty : w1[j];
+    const uint32_t lo = a < c ? a : c, hi = a < c ? c : a;  // kEmpty sorts last
+    if (lo < v) {
+      par[j] = lo;
+      lo_[j] = lo;
+      ++linked;
+      rec[2 * j] = hi;
+      rec[2 * j + 1] = kEmpty;
+    } else {
+      par[j] = v;
+      lo_[j] = kEmpty;
+      rec[2 * j] = lo;
+      rec[2 * j + 1] = hi;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    slot[r] = rec[r] != kEmpty ? atomicAdd(&cnt[(rec[r] >> shift) & (kKxGroups - 1)], 1u) : 0u;
+  // parents and forest slots of the four vertices
+  if ((vec & 1) && v0 + 4 <= n) {
+    *reinterpret_cast<uint4*>(P + v0) = make_uint4(par[0], par[1], par[2], par[3]);
+    if (fu) {
+      const uint32_t v = (uint32_t)v0;
+      *reinterpret_cast<uint4*>(fu + v0) =
+          make_uint4(lo_[0] != kEmpty ? v : kEmpty, lo_[1] != kEmpty ? v + 1 : kEmpty,
+                     lo_[2] != kEmpty ? v + 2 : kEmpty, lo_[3] != kEmpty ? v + 3 : kEmpty);
+      *reinterpret_cast<uint4*>(fv + v0) = make_uint4(lo_[0], lo_[1], lo_[2], lo_[3]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (v0 + j < n) {
+        P[v0 + j] = par[j];
+        if (fu) {
+          fu[v0 + j] = lo_[j] != kEmpty ? (uint32_t)(v0 + j) : kEmpty;
+          fv[v0 + j] = lo_[j];
+        }
+      }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t at = 0;
+    for (uint32_t g = 0; g < kKxGroups; ++g) {
+      pos[g] = at;
+      at += cnt[g];
+    }
+    pos[kKxGroups] = at;
+  }
+  if (threadIdx.x < kKxGroups) hdr[(uint64_t)blockIdx.x * kKxGroups + threadIdx.x] = cnt[threadIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    if (rec[r] != kEmpty) {
+      const uint32_t at = pos[(rec[r] >> shift) & (kKxGroups - 1)] + slot[r];
+      s_src[at] = (uint32_t)(v0 + r / 2);
+      s_dst[at] = rec[r];
+    }
+  __syncthreads();
+  const uint32_t total = pos[kKxGroups];
+  const uint64_t out = (uint64_t)blockIdx.x * kKxCap;
+  for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) {
+    rsrc[out + i] = s_src[i];
+    rdst[out + i] = s_dst[i];
+  }
+  if (stats) {
+    sampled = wave_sum(sampled);
+    linked = wave_sum(linked);
+    if (lane() == 0) {
+      if (sampled) atomicAdd(&stats->stat_sampled, sampled);
+      if (linked) atomicAdd(&stats->stat_hooks, linked);
+    }
+  }
+}
+
+// Pre-link roots of one chunk: P[v] is pointed at its root (only this
+// workgroup writes the chunk's parent words, and no link runs in this kernel,
+// so every value any lane reads is an ancestor), and each residual record gets
+// the root of its first endpoint (rroot, same layout as the records).
+__global__ void __launch_bounds__(256) k_kx_flatten(uint32_t* P, uint32_t n,
+                                                    const uint32_t* __restrict__ rsrc,
+                                                    const uint32_t* __restrict__ hdr,
+                                                    uint32_t* rroot) {
+  __shared__ uint32_t R[kKxChunk];
+  const uint64_t base = (uint64_t)blockIdx.x * kKxChunk;
+  const uint32_t len = (uint32_t)min<uint64_t>(kKxChunk, n - base);
+  uint32_t p[4], r[4];
+  bool done[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t i = 4 * threadIdx.x + j;
+    p[j] = i < len ? P[base + i] : 0u;
+    r[j] = p[j];
+    done[j] = i >= len || p[j] == base + i;
+  }
+  // the four chases advance together (independent loads in flight)
+  for (;;) {
+    bool more = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!done[j]) {
+        const uint32_t q = ld(&P[r[j]]);
+        if (q == r[j]) done[j] = true;
+        else r[j] = q;
+        more = more || !done[j];
+      }
+    if (!more) break;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t i = 4 * threadIdx.x + j;
+    if (i < len) {
+      R[i] = r[j];
+      if (r[j] != p[j]) P[base + i] = r[j];
+    }
+  }
+  __syncthreads();
+  const uint32_t* h = hdr + (uint64_t)blockIdx.x * kKxGroups;
+  uint32_t total = 0;
+#pragma unroll
+  for (uint32_t g = 0; g < kKxGroups; ++g) total += h[g];
+  const uint64_t at = (uint64_t)blockIdx.x * kKxCap;
+  for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) rroot[at + i] = R[rsrc[at + i] - base];
+}
+
+// Union pass over the residual records, XCD by XCD (see above).  Each lane
+// takes two records at a time and loads both endpoints' parents of both
+// before uniting them (a parent value a slot has held is a valid start for
+// the root-based rules).
+template <class R>
+__global__ void __launch_bounds__(256) k_kx_unite(const uint32_t* __restrict__ rsrc,
+                                                  const uint32_t* __restrict__ rdst,
+                                                  const uint32_t* __restrict__ rroot,
+                                                  const uint32_t* __restrict__ hdr,
+                                                  uint32_t chunks, int from_vertex, Ctrl* c,
+                                                  LinkCtx lc) {
+  __shared__ uint32_t s_item, s_grp;
+  __shared__ uint32_t seg[kKxItem], pre[kKxItem + 1];
+  const uint32_t items = (chunks + kKxItem - 1) / kKxItem;
+  const uint32_t home = xcc_id();
+  uint32_t tried = 0;  // thread 0 only: queues found empty, in order from home
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t t = kEmpty, g = home;
+      while (tried < kKxGroups) {
+        g = (home + tried) & (kKxGroups - 1);
+        t = atomicAdd(&c->kx_queue[g], 1u);
+        if (t < items) break;
+        t = kEmpty;
+        ++tried;
+      }
+      s_item = t;
+      s_grp = g;
+    }
+    __syncthreads();
+    const uint32_t item = s_item, g = s_grp;
+    if (item == kEmpty) break;
+    if (threadIdx.x < 64) {
+      // the group's segment in each chunk of the item, and a prefix of the lengths
+      const uint32_t ch = item * kKxItem + lane();
+      uint32_t start = 0, cnt = 0;
+      if (lane() < kKxItem && ch < chunks) {
+        const uint32_t* h = hdr + (uint64_t)ch * kKxGroups;
+        for (uint32_t x = 0; x < g; ++x) start += h[x];
+        cnt = h[g];
+      }
+      uint32_t total;
+      const uint32_t ex = wave_exclusive(cnt, &total);
+      if (lane() < kKxItem) {
+        seg[lane()] = start;
+        pre[lane()] = ex;
+      }
+      if (lane() == 0) pre[kKxItem] = total;
+    }
+    __syncthreads();
+    const uint32_t total = pre[kKxItem];
+    auto locate = [&](uint32_t j) -> uint64_t {
+      uint32_t lo = 0, hi = kKxItem;  // pre[lo] <= j < pre[hi]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= j) lo = mid;
+        else hi = mid;
+      }
+      return (uint64_t)(item * kKxItem + lo) * kKxCap + seg[lo] + (j - pre[lo]);
+    };
+    for (uint32_t j = threadIdx.x; j < total; j += 2 * blockDim.x) {
+      const uint32_t j2 = j + blockDim.x;
+      const uint64_t i1 = locate(j);
+      const uint64_t i2 = j2 < total ? locate(j2) : i1;
+      const uint32_t r1 = __builtin_nontemporal_load(&rroot[i1]);
+      const uint32_t w1 = __builtin_nontemporal_load(&rdst[i1]);
+      const uint32_t r2 = __builtin_nontemporal_load(&rroot[i2]);
+      const uint32_t w2 = __builtin_nontemporal_load(&rdst[i2]);
+      const uint32_t e1 = (from_vertex || lc.fu) ? __builtin_nontemporal_load(&rsrc[i1]) : r1;
+      const uint32_t e2 = (from_vertex || lc.fu) ? __builtin_nontemporal_load(&rsrc[i2]) : r2;
+      const uint32_t pw1 = ld(&lc.P[w1]), pw2 = ld(&lc.P[w2]);
+      if (from_vertex) {
+        // from the endpoint itself, whose parent was the root r (flattened)
+        R::unite_edge(lc, e1, w1, r1, pw1, e1);
+        if (j2 < total) R::unite_edge(lc, e2, w2, r2, pw2, e2);
+      } else {
+        const uint32_t pr1 = ld(&lc.P[r1]), pr2 = ld(&lc.P[r2]);
+        R::unite_edge(lc, r1, w1, pr1, pw1, e1);
+        if (j2 < total) R::unite_edge(lc, r2, w2, pr2, pw2, e2);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1125,7 +1428,61 @@ __global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* vis
     c->frontier_edges[0] = deg;
     c->frontier_edges[1] = 0;
     c->explored_edges = deg;
+    c->bfs_as_queue = 1;
+    c->bfs_mode = 1;
+    c->bfs_levels = 0;
   }
+}
+
+// One BFS level's decision, on the device (so that the host enqueues several
+// levels between checks): stop when the frontier `cur` is empty; otherwise
+// pick the direction with the direction-optimising rule of Beamer, Asanovic
+// and Patterson (SC'12) -- switch to bottom-up once the frontier's edges
+// exceed 1/alpha of the unexplored edges, back to top-down once the frontier
+// holds fewer than n/beta vertices; alpha = 14, beta = 24, compared in
+// integers -- note which representation change the level needs first, and
+// clear the counters of frontier `nxt`.  Every later kernel of the level
+// reads bfs_mode and returns at once when the level is not its kind.
+__global__ void k_bfs_decide(Ctrl* c, uint32_t cur, uint64_t m, uint32_t n) {
+  __shared__ uint32_t run;
+  if (threadIdx.x == 0) {
+    const uint32_t count = c->frontier_count[cur];
+    run = c->bfs_mode != 0 && count != 0;
+    if (!run) {
+      c->bfs_mode = 0;
+    } else {
+      const uint64_t m_f = c->frontier_edges[cur];
+      const uint64_t m_u = m > c->explored_edges ? m - c->explored_edges : 0;
+      bool bu = c->bfs_mode == 2;
+      if (!bu && 14 * m_f > m_u) bu = true;
+      else if (bu && 24ull * count < n) bu = false;
+      const bool q = c->bfs_as_queue != 0;
+      c->bfs_convert = bu ? (q ? 1u : 0u) : (q ? 0u : 2u);
+      c->bfs_mode = bu ? 2u : 1u;
+      c->bfs_as_queue = bu ? 0u : 1u;  // after this level
+      ++c->bfs_levels;
+    }
+  }
+  __syncthreads();
+  if (!run) return;
+  const uint32_t nxt = cur ^ 1u;
+  for (uint32_t i = threadIdx.x; i < kSubLists; i += blockDim.x) {
+    c->small_cnt[i] = 0;
+    c->medium_cnt[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    c->frontier_count[nxt] = 0;
+    c->frontier_edges[nxt] = 0;
+    c->seg_count = 0;
+    c->queue_cursor = 0;
+  }
+}
+
+// Fill of a frontier bitmap when this level is bottom-up (and, with
+// need_convert, only when the frontier is first turned from a queue into bits).
+__global__ void k_bfs_clear_bits(uint32_t* bits, uint32_t words, const Ctrl* c, int need_convert) {
+  if (c->bfs_mode != 2 || (need_convert && c->bfs_convert != 1)) return;
+  for (uint64_t i = gtid(); i < words; i += wave_stride()) bits[i] = 0u;
 }
 
 __global__ void k_bfs_level_reset(Ctrl* c, uint32_t nxt) {
@@ -1146,6 +1503,7 @@ __global__ void k_bfs_level_reset(Ctrl* c, uint32_t nxt) {
 template <typename OffT>
 __global__ void k_bfs_td_split(const OffT* __restrict__ off, const uint32_t* __restrict__ queue,
                                Ctrl* c, uint32_t cur, WorkLists wl) {
+  if (c->bfs_mode != 1) return;
   const uint32_t count = c->frontier_count[cur];
   for (uint64_t base = wave_base(); base < count; base += wave_stride()) {
     const uint64_t i = base + lane();
@@ -1159,43 +1517,73 @@ __global__ void k_bfs_td_split(const OffT* __restrict__ off, const uint32_t* __r
   }
 }
 
-// Visit w from u: claim its visited bit; new vertices are appended to the next
-// queue (one atomic per wave) and record their BFS-tree edge.  All 64 lanes
-// must be active; `valid` masks the lanes without an edge this round.
-template <typename OffT>
-__device__ __forceinline__ void bfs_visit(const OffT* __restrict__ off, bool valid, uint32_t u,
-                                          uint32_t w, uint32_t* visited, uint32_t* queue_out,
-                                          Ctrl* c, uint32_t nxt, uint32_t* fu, uint32_t* fv,
-                                          unsigned long long* edges) {
-  bool fresh = false;
-  if (valid) {
-    const uint32_t bit = 1u << (w & 31);
-    if (!(ld(&visited[w >> 5]) & bit)) fresh = !(atomicOr(&visited[w >> 5], bit) & bit);
-  }
-  bool any;
-  const uint32_t slot = wave_append(&c->frontier_count[nxt], fresh, &any);
-  if (fresh) {
-    queue_out[slot] = w;
-    *edges += (uint64_t)off[w + 1] - off[w];
-    if (fu) {
-      fu[w] = u;
-      fv[w] = w;
-    }
-  }
+// Top-down level with the next frontier staged in LDS: a wave claims the
+// visited bits of its neighbours, appends the fresh vertices to its
+// workgroup's LDS buffer (one LDS atomic per wave), and the workgroup copies
+// the buffer to the next queue with one global atomic when it fills up and at
+// the end (the queue's counter is a single address, where device atomics
+// serialise).  Fresh vertices record their BFS-tree edge.
+constexpr uint32_t kBfsStage = 4096;
+
+// Claim w from u (valid lanes); returns whether this lane made w visited.
+__device__ __forceinline__ bool bfs_claim(bool valid, uint32_t w, uint32_t* visited) {
+  if (!valid) return false;
+  const uint32_t bit = 1u << (w & 31);
+  if (ld(&visited[w >> 5]) & bit) return false;
+  return !(atomicOr(&visited[w >> 5], bit) & bit);
 }
 
 template <typename OffT>
-__global__ void k_bfs_td(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                         WorkLists wl, Ctrl* c, uint32_t nxt, uint32_t* visited,
-                         uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
+__global__ void __launch_bounds__(256) k_bfs_td(const OffT* __restrict__ off,
+                                                const uint32_t* __restrict__ nbrs, WorkLists wl,
+                                                Ctrl* c, uint32_t nxt, uint32_t* visited,
+                                                uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
   __shared__ uint32_t pre_s[kSubLists + 1], pre_m[kSubLists + 1];
+  __shared__ uint32_t stage[kBfsStage];
+  __shared__ uint32_t staged, base_out;
+  if (c->bfs_mode != 1) return;
   wl_prefix(c->small_cnt, pre_s);
   wl_prefix(c->medium_cnt, pre_m);
+  if (threadIdx.x == 0) staged = 0;
   __syncthreads();
   const uint32_t S = pre_s[kSubLists], M = pre_m[kSubLists], G = c->seg_count;
   unsigned long long edges = 0;
-  for (uint64_t base = wave_base(); base < S; base += wave_stride()) {
-    const uint64_t i = base + lane();
+  // Append the lanes' fresh vertices (all 64 lanes active) to the stage, or,
+  // when it has no room, straight to the queue.
+  auto emit = [&](bool fresh, uint32_t u, uint32_t w) {
+    const unsigned long long mask = __ballot(fresh);
+    if (!mask) return;
+    const uint32_t cnt = (uint32_t)__popcll(mask);
+    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane()) - 1));
+    const uint32_t leader = __ffsll(mask) - 1;
+    // the leader reserves cnt stage slots if they fit, else cnt queue slots
+    uint32_t at = 0, in_stage = 0;
+    if (lane() == leader) {
+      uint32_t old = __hip_atomic_load(&staged, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      while (old + cnt <= kBfsStage) {
+        if (__hip_atomic_compare_exchange_strong(&staged, &old, old + cnt, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+          at = old;
+          in_stage = 1;
+          break;
+        }
+      }
+      if (!in_stage) at = atomicAdd(&c->frontier_count[nxt], cnt);
+    }
+    at = __shfl(at, leader);
+    in_stage = __shfl(in_stage, leader);
+    if (fresh) {
+      if (in_stage) stage[at + rank] = w;
+      else queue_out[at + rank] = w;  // straight to the queue
+      edges += (uint64_t)off[w + 1] - off[w];
+      if (fu) {
+        fu[w] = u;
+        fv[w] = w;
+      }
+    }
+  };
+  for (uint64_t b0 = wave_base(); b0 < S; b0 += wave_stride()) {
+    const uint64_t i = b0 + lane();
     uint32_t u = 0;
     uint64_t b = 0, deg = 0;
     if (i < S) {
@@ -1205,19 +1593,19 @@ __global__ void k_bfs_td(const OffT* __restrict__ off, const uint32_t* __restric
     }
     for (uint32_t j = 0; __ballot(j < deg); ++j) {
       const bool valid = j < deg;
-      bfs_visit(off, valid, u, valid ? nbrs[b + j] : 0u, visited, queue_out, c, nxt, fu, fv,
-                &edges);
+      const uint32_t w = valid ? nbrs[b + j] : 0u;
+      emit(bfs_claim(valid, w, visited), u, w);
     }
   }
-  for (uint64_t w = wave_index(); w < (uint64_t)M + G; w += wave_count()) {
+  for (uint64_t wi = wave_index(); wi < (uint64_t)M + G; wi += wave_count()) {
     uint32_t u;
     uint64_t b, e;
-    if (w < M) {
-      u = wl_get(wl.medium, wl.cap, pre_m, (uint32_t)w);
+    if (wi < M) {
+      u = wl_get(wl.medium, wl.cap, pre_m, (uint32_t)wi);
       b = off[u];
       e = off[u + 1];
     } else {
-      const uint2 sg = wl.segs[w - M];
+      const uint2 sg = wl.segs[wi - M];
       u = sg.x;
       b = (uint64_t)off[u] + (uint64_t)sg.y * kSeg;
       e = off[u + 1];
@@ -1226,9 +1614,15 @@ __global__ void k_bfs_td(const OffT* __restrict__ off, const uint32_t* __restric
     for (uint64_t x0 = b; x0 < e; x0 += 64) {
       const uint64_t x = x0 + lane();
       const bool valid = x < e;
-      bfs_visit(off, valid, u, valid ? nbrs[x] : 0u, visited, queue_out, c, nxt, fu, fv, &edges);
+      const uint32_t w = valid ? nbrs[x] : 0u;
+      emit(bfs_claim(valid, w, visited), u, w);
     }
   }
+  __syncthreads();
+  const uint32_t kept = staged;
+  if (threadIdx.x == 0 && kept) base_out = atomicAdd(&c->frontier_count[nxt], kept);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kept; i += blockDim.x) queue_out[base_out + i] = stage[i];
   edges = wave_sum(edges);
   if (lane() == 0 && edges) {
     atomicAdd(&c->frontier_edges[nxt], edges);
@@ -1238,6 +1632,7 @@ __global__ void k_bfs_td(const OffT* __restrict__ off, const uint32_t* __restric
 
 __global__ void k_queue_to_bits(const uint32_t* __restrict__ queue, const Ctrl* c, uint32_t cur,
                                 uint32_t* bits) {
+  if (c->bfs_mode != 2 || c->bfs_convert != 1) return;
   const uint32_t count = c->frontier_count[cur];
   for (uint64_t i = gtid(); i < count; i += wave_stride()) {
     const uint32_t w = queue[i];
@@ -1248,6 +1643,7 @@ __global__ void k_queue_to_bits(const uint32_t* __restrict__ queue, const Ctrl* 
 // Rebuild a frontier queue from its bitmap (queue_cursor is the append cursor).
 __global__ void k_bits_to_queue(const uint32_t* __restrict__ bits, uint32_t words, Ctrl* c,
                                 uint32_t* queue) {
+  if (c->bfs_mode != 1 || c->bfs_convert != 2) return;
   for (uint64_t base = wave_base(); base < words; base += wave_stride()) {
     const uint64_t i = base + lane();
     uint32_t word = i < words ? bits[i] : 0u;
@@ -1265,6 +1661,7 @@ template <typename OffT>
 __global__ void k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
                          uint32_t n, uint32_t* visited, const uint32_t* __restrict__ fr_in,
                          uint32_t* fr_out, Ctrl* c, uint32_t nxt, uint32_t* fu, uint32_t* fv) {
+  if (c->bfs_mode != 2) return;
   unsigned long long found = 0, found_edges = 0;
   for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
     const uint64_t v = base + lane();
@@ -1366,8 +1763,19 @@ bool kout_flat_applies(const gconn_options& o) {
   return !kout_local_applies(o) && o.schedule == 5 && o.sample == GCONN_SAMPLE_KOUT &&
          !o.kout_random && o.k <= 2;
 }
+// The XCD-bucketed k-out passes (k_kx_stream, k_kx_flatten, k_kx_unite).
+bool kout_xcd_applies(const gconn_options& o) {
+  return !kout_local_applies(o) && o.schedule == 6 && o.sample == GCONN_SAMPLE_KOUT &&
+         !o.kout_random && o.k <= 2;
+}
+// Id-range width (log2) of the XCD groups: at least 512 ranges per graph.
+uint32_t kx_shift(uint32_t n) {
+  uint32_t bits = 0;
+  while (bits < 32 && (1ull << bits) < n) ++bits;
+  return bits > 14 ? bits - 9 : 5;
+}
 bool kout_prelink_applies(const gconn_options& o) {
-  return !kout_local_applies(o) && (o.kout_prelink || kout_flat_applies(o)) &&
+  return !kout_local_applies(o) && !kout_xcd_applies(o) && (o.kout_prelink || kout_flat_applies(o)) &&
          o.sample == GCONN_SAMPLE_KOUT && !o.kout_random && o.k <= 2;
 }
 
@@ -1529,6 +1937,39 @@ struct Run {
            !g.offsets_64 && o.schedule == 2;
   }
 
+  // Id range of the local-first k-out: the largest power of two up to
+  // kLocalRangeMax whose parents fit the device's LDS per workgroup (the
+  // kernel's dynamic LDS limit is raised to match once per process).
+  template <typename OffT>
+  static gconn_status local_range(uint32_t* out) {
+    static std::mutex mu;
+    static uint32_t cached = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cached) {
+      int dev = 0, lds = 65536;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+              hipSuccess) {
+        (void)hipGetLastError();
+        lds = 65536;
+      }
+      uint32_t r = kLocalRangeMax;
+      while (r > kLocalRangeMin && 4ull * r > (uint64_t)lds) r >>= 1;
+      if (4ull * r > 65536) {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&k_kout_local<OffT>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(4 * r));
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          r = 16384;  // 64 KB: always allowed
+        }
+      }
+      cached = r;
+    }
+    *out = cached;
+    return GCONN_OK;
+  }
+
   template <typename OffT>
   gconn_status sample_phase() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
@@ -1538,14 +1979,38 @@ struct Run {
     if (o.sample == GCONN_SAMPLE_KOUT) {
       if (kout_local_applies(o)) {
         uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
-        const uint32_t ranges = (uint32_t)((n + kLocalRange - 1) / kLocalRange);
-        k_kout_local<OffT><<<ranges, 512, 0, s>>>(off, g.nbrs, n, o.k, P, res, fu, fv,
-                                                  o.kout_local ? 1 : 0, st);
+        uint32_t range = kLocalRangeMin;
+        GCONN_TRY(local_range<OffT>(&range));
+        const uint32_t ranges = (uint32_t)((n + range - 1) / range);
+        k_kout_local<OffT><<<ranges, 1024, 4 * range, s>>>(off, g.nbrs, n, o.k, range, P, res,
+                                                           fu, fv, o.kout_local ? 1 : 0, st);
         GCONN_LAUNCHED("k_kout_local");
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
           using R = decltype(rule);
           k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n, link_ctx());
           GCONN_LAUNCHED("k_kout_residual");
+          return GCONN_OK;
+        }));
+      } else if (kout_xcd_applies(o)) {
+        uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.kx_src);
+        uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.kx_dst);
+        uint32_t* rroot = reinterpret_cast<uint32_t*>(ws + L.kx_root);
+        uint32_t* hdr = reinterpret_cast<uint32_t*>(ws + L.kx_hdr);
+        const uint32_t chunks = (uint32_t)((n + kKxChunk - 1) / kKxChunk);
+        const int vec = (((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(fu) |
+                           reinterpret_cast<uintptr_t>(fv)) % 16) == 0 ? 1 : 0) |
+                        ((sizeof(OffT) == 4 && reinterpret_cast<uintptr_t>(off) % 16 == 0) ? 2 : 0);
+        k_kx_stream<OffT><<<chunks, 256, 0, s>>>(off, g.nbrs, n, o.k, kx_shift(n), P, fu, fv,
+                                                 rsrc, rdst, hdr, vec, st);
+        GCONN_LAUNCHED("k_kx_stream");
+        k_kx_flatten<<<chunks, 256, 0, s>>>(P, n, rsrc, hdr, rroot);
+        GCONN_LAUNCHED("k_kx_flatten");
+        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+          using R = decltype(rule);
+          const uint32_t grid = persistent_grid(k_kx_unite<R>, 256);
+          k_kx_unite<R><<<grid, 256, 0, s>>>(rsrc, rdst, rroot, hdr, chunks, o.kout_prelink, ctrl,
+                                              link_ctx());
+          GCONN_LAUNCHED("k_kx_unite");
           return GCONN_OK;
         }));
       } else if (kout_flat_applies(o)) {
@@ -1647,50 +2112,52 @@ struct Run {
     GCONN_LAUNCHED("k_bfs_argmax");
     k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0]);
     GCONN_LAUNCHED("k_bfs_start");
-    // Direction-optimising parameters (Beamer, Asanovic, Patterson, SC'12).
-    const double alpha = 14.0, beta = 24.0;
-    bool bottom_up = false;
-    bool have_queue = true;  // frontier `cur` is held as a queue (else as bits)
-    Ctrl h;
-    const uint32_t td_grid = persistent_grid(k_bfs_td<OffT>, block);
-    for (uint32_t level = 0;; ++level) {
-      const uint32_t cur = level & 1, nxt = cur ^ 1;
-      GCONN_TRY(read_ctrl(&h));
-      if (h.frontier_count[cur] == 0) break;
-      ++rounds;
-      const double m_f = (double)h.frontier_edges[cur];
-      const double m_u = (double)g.m - (double)h.explored_edges;
-      if (!bottom_up && m_f > m_u / alpha) bottom_up = true;
-      else if (bottom_up && (double)h.frontier_count[cur] < (double)n / beta) bottom_up = false;
-      k_bfs_level_reset<<<1, 128, 0, s>>>(ctrl, nxt);
-      GCONN_LAUNCHED("k_bfs_level_reset");
-      if (bottom_up) {
-        if (have_queue) {
-          k_fill<<<gridN(words), block, 0, s>>>(bits[cur], 0u, words);
-          GCONN_LAUNCHED("k_fill(bits)");
-          k_queue_to_bits<<<gridN(h.frontier_count[cur]), block, 0, s>>>(queue[cur], ctrl, cur,
-                                                                          bits[cur]);
-          GCONN_LAUNCHED("k_queue_to_bits");
-        }
-        k_fill<<<gridN(words), block, 0, s>>>(bits[nxt], 0u, words);
-        GCONN_LAUNCHED("k_fill(bits)");
-        k_bfs_bu<OffT><<<gridN(n), block, 0, s>>>(off, g.nbrs, n, visited, bits[cur], bits[nxt],
-                                                  ctrl, nxt, fu, fv);
+    // Levels run kRoundsPerSync at a time between host checks: each level's
+    // direction and representation changes are decided on the device
+    // (k_bfs_decide), every kernel of the level has a fixed grid and returns
+    // at once when the level is not its kind, and once the frontier is empty
+    // all of them do.
+    const uint32_t td_grid = persistent_grid(k_bfs_td<OffT>, 256);
+    const uint32_t fixed = std::min<uint32_t>(gridN(n), kPersistentBlocks);
+    const uint32_t wgrid = std::min<uint32_t>(gridN(words), kPersistentBlocks);
+    for (uint64_t level = 0;; level += kRoundsPerSync) {
+      for (int j = 0; j < kRoundsPerSync; ++j) {
+        const uint32_t cur = (uint32_t)((level + j) & 1), nxt = cur ^ 1;
+        k_bfs_decide<<<1, 128, 0, s>>>(ctrl, cur, g.m, n);
+        GCONN_LAUNCHED("k_bfs_decide");
+        // bottom-up: the frontier as bits (from the queue if it was one)
+        k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, 1);
+        GCONN_LAUNCHED("k_bfs_clear_bits");
+        k_queue_to_bits<<<fixed, block, 0, s>>>(queue[cur], ctrl, cur, bits[cur]);
+        GCONN_LAUNCHED("k_queue_to_bits");
+        k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[nxt], words, ctrl, 0);
+        GCONN_LAUNCHED("k_bfs_clear_bits");
+        k_bfs_bu<OffT><<<fixed, block, 0, s>>>(off, g.nbrs, n, visited, bits[cur], bits[nxt],
+                                               ctrl, nxt, fu, fv);
         GCONN_LAUNCHED("k_bfs_bu");
-        have_queue = false;
-      } else {
-        if (!have_queue) {
-          k_bits_to_queue<<<gridN(words), block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
-          GCONN_LAUNCHED("k_bits_to_queue");
-        }
-        k_bfs_td_split<OffT><<<gridN(h.frontier_count[cur]), block, 0, s>>>(off, queue[cur], ctrl,
-                                                                             cur, wl);
+        // top-down: the frontier as a queue (from the bits if it was those)
+        k_bits_to_queue<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
+        GCONN_LAUNCHED("k_bits_to_queue");
+        k_bfs_td_split<OffT><<<fixed, block, 0, s>>>(off, queue[cur], ctrl, cur, wl);
         GCONN_LAUNCHED("k_bfs_td_split");
-        k_bfs_td<OffT><<<td_grid, block, 0, s>>>(off, g.nbrs, wl, ctrl, nxt, visited, queue[nxt],
-                                                 fu, fv);
+        k_bfs_td<OffT><<<td_grid, 256, 0, s>>>(off, g.nbrs, wl, ctrl, nxt, visited, queue[nxt],
+                                               fu, fv);
         GCONN_LAUNCHED("k_bfs_td");
-        have_queue = true;
       }
+      uint32_t mode = 0;
+      GCONN_HIP(hipMemcpyAsync(&mode, &ctrl->bfs_mode, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s));
+      GCONN_HIP(hipStreamSynchronize(s));
+      if (mode == 0) break;
+      if (level + kRoundsPerSync > (uint64_t)n + kRoundsPerSync)
+        return fail(GCONN_EDEVICE, "BFS did not finish within n levels");
+    }
+    {
+      uint32_t levels = 0;
+      GCONN_HIP(hipMemcpyAsync(&levels, &ctrl->bfs_levels, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, s));
+      GCONN_HIP(hipStreamSynchronize(s));
+      rounds = levels;
     }
     k_bfs_min<<<gridN(words), block, 0, s>>>(visited, words, ctrl);
     GCONN_LAUNCHED("k_bfs_min");
@@ -2037,6 +2504,13 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
   }
   if (needs_claims(o.link)) L.hooks = take(4 * n);
   if (csr && (kout_prelink_applies(o) || kout_local_applies(o))) L.resid = take(8 * n);
+  if (csr && kout_xcd_applies(o)) {
+    const uint64_t chunks = (n + kKxChunk - 1) / kKxChunk;
+    L.kx_src = take(4 * chunks * kKxCap);
+    L.kx_dst = take(4 * chunks * kKxCap);
+    L.kx_root = take(4 * chunks * kKxCap);
+    L.kx_hdr = take(4 * chunks * kKxGroups);
+  }
   const bool iterative =
       o.link == GCONN_LINK_SV || o.link == GCONN_LINK_LT || o.link == GCONN_LINK_LP;
   if (iterative) {
@@ -2089,9 +2563,16 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
   GCONN_TRY(prof_mark(kPhaseInit, true, s));
   const bool vec = (reinterpret_cast<uintptr_t>(P) % 16) == 0 &&
                    (!fu || ((reinterpret_cast<uintptr_t>(fu) | reinterpret_cast<uintptr_t>(fv)) % 16) == 0);
-  k_init<<<grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), block), block, 0, s>>>(run.ctrl, P, n, fu,
-                                                                                fv, vec ? 1 : 0);
-  GCONN_LAUNCHED("k_init");
+  // The XCD-bucketed k-out writes every parent and forest slot itself.
+  const bool kx_writes_all = g.format == GCONN_CSR && n > 0 && g.m > 0 && kout_xcd_applies(o);
+  if (kx_writes_all) {
+    k_ctrl_init<<<1, 256, 0, s>>>(run.ctrl);
+    GCONN_LAUNCHED("k_ctrl_init");
+  } else {
+    k_init<<<grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), block), block, 0, s>>>(
+        run.ctrl, P, n, fu, fv, vec ? 1 : 0);
+    GCONN_LAUNCHED("k_init");
+  }
   if (run.hooks) GCONN_TRY(launch_fill(run.hooks, kEmpty, n, s));
   GCONN_TRY(prof_mark(kPhaseInit, false, s));
 

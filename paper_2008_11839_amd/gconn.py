@@ -23,7 +23,7 @@ LINK = {"async": 0, "hooks": 1, "early": 2, "rem_cas": 3, "ecl": 4, "sv": 5, "lt
         "afforest": 8, "rem_lock": 9, "jtb": 10}
 FIND = {"naive": 0, "split": 1, "halve": 2, "compress": 3, "two_try_split": 4}
 SPLICE = {"split_one": 0, "halve_one": 1, "splice_atomic": 2}
-SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3, "twopass": 4, "flat": 5}
+SCHEDULE = {"auto": 0, "lane": 1, "step": 2, "pipe": 3, "twopass": 4, "flat": 5, "xcd": 6}
 LT_VARIANTS = ["CUSA", "CRSA", "PUSA", "PRSA", "PUS", "PRS", "EUSA", "EUS",
                "CUFA", "CRFA", "PUFA", "PRFA", "PUF", "PRF", "EUFA", "EUF"]
 STATUS = {0: "GCONN_OK", -1: "GCONN_EINVAL", -2: "GCONN_ENOMEM", -3: "GCONN_EDEVICE",
@@ -97,7 +97,7 @@ EXPORTS = ["gconn_server_create", "gconn_server_submit", "gconn_server_wait",
            "gconn_inc_workspace_size", "gconn_inc_create", "gconn_inc_insert_batch",
            "gconn_inc_query_batch", "gconn_inc_mixed_batch", "gconn_inc_labels", "gconn_inc_destroy",
            "gconn_cc_capture", "gconn_cc_batch_capture", "gconn_exec_launch", "gconn_exec_destroy",
-           "gconn_status_string", "gconn_last_error", "gconn_version"]
+           "gconn_status_string", "gconn_last_error", "gconn_version", "gconn_diag_random_access"]
 
 _lib = None
 
@@ -120,6 +120,9 @@ def lib() -> ctypes.CDLL:
         L.gconn_cc.argtypes = [gp, vp, vp, sz, op, stp, vp]
         L.gconn_cc_noalloc.restype = ctypes.c_int
         L.gconn_cc_noalloc.argtypes = [gp, vp, op, stp, vp]
+        L.gconn_diag_random_access.restype = ctypes.c_int
+        L.gconn_diag_random_access.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                               vp, ctypes.c_uint32, vp]
         L.gconn_spanning_forest.restype = ctypes.c_int
         L.gconn_spanning_forest.argtypes = [gp, vp, vp, vp, vp, sz, op, stp, vp]
         L.gconn_inc_workspace_size.restype = ctypes.c_int
@@ -324,6 +327,14 @@ def cc(g: DeviceGraph, labels: torch.Tensor | None = None, options: Options | No
                           workspace.numel(), ctypes.byref(o), ctypes.byref(st) if st else None,
                           _stream(stream)))
     return (labels, _stats_dict(st)) if stats else labels
+
+
+def diag_random_access(table: torch.Tensor, kind: int, accesses: int, sink: torch.Tensor,
+                       stream=None) -> None:
+    """gconn_diag_random_access: one kernel of `accesses` random 4-byte
+    accesses to `table` (kind 0 cached loads, 1 coherent loads, 2 CAS)."""
+    _check(lib().gconn_diag_random_access(_ptr(table), table.numel(), kind, accesses, _ptr(sink),
+                                          sink.numel(), _stream(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # GCONN_NOALLOC_SCRATCH_BYTES

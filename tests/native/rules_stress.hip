@@ -19,7 +19,8 @@
 // that address, and otherwise reads memory and refreshes the copy.  The
 // thread's own CAS and stores do not update its copy, so it can even read back
 // a value older than one it wrote.  Device-coherent reads (ld_agent) and the
-// atomics always see memory.
+// atomics always see memory.  Every other union then starts from parent values
+// read through this model (Rule::unite_from), as the prefetching kernels do.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -66,8 +67,17 @@ void run(const std::vector<uint32_t>& e, LinkCtx c, int threads) {
   std::vector<std::thread> ts;
   for (int t = 0; t < threads; ++t)
     ts.emplace_back([&, t] {
-      // interleaved slices so that threads race on the same regions
-      for (size_t i = t; i < m; i += threads) R::unite(c, e[2 * i], e[2 * i + 1]);
+      // interleaved slices so that threads race on the same regions; with
+      // stale reads modelled, every other union starts from parent values
+      // read through the stale model (unite_from: the starting points the
+      // prefetching kernels hand over)
+      for (size_t i = t; i < m; i += threads) {
+        const uint32_t u = e[2 * i], v = e[2 * i + 1];
+        if (stale::g_percent > 0 && (i & 1))
+          R::unite_from(c, u, v, ld(&c.P[u]), ld(&c.P[v]));
+        else
+          R::unite(c, u, v);
+      }
     });
   for (auto& th : ts) th.join();
 }

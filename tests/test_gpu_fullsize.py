@@ -25,6 +25,10 @@ WORK = {"rmat24_ef16_s1": lambda: graphgen.rmat(24, 16, 1),
         "grid3d_256_p06_s1": lambda: graphgen.grid3d(256, 256, 256, 0.6, 1)}
 CONFIGS = [dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic"),  # benchmark
            dict(sample="kout", link="rem_cas", find="split", splice="split_one"),  # its forest
+           dict(sample="kout", link="rem_cas", find="split", splice="split_one", schedule="xcd"),
+           dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic",
+                schedule="xcd"),
+           dict(sample="kout", link="rem_cas", find="split", splice="split_one", schedule="flat"),
            dict(sample="kout", link="rem_cas", find="halve", kout_prelink=True),
            dict(sample="kout", link="rem_cas", find="split", kout_local=True),
            dict(sample="kout", link="rem_cas", find="split", schedule="twopass"),

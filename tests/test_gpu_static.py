@@ -97,6 +97,47 @@ def test_union_find_rules_all_samplers(cases):
                     assert np.array_equal(got, want), (name, sample, link, find, splice, ac)
 
 
+def test_xcd_kout_every_union_rule(cases):
+    """The XCD-bucketed k-out schedule (pre-link, flatten, per-XCD record
+    groups) with every union-find rule: the oracle's labels, sampled-edge
+    count, L_max and active set, and -- for the root-based rules -- a valid
+    forest filling exactly the non-minimum slots."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    for name, (C, dg, want) in cases.items():
+        roots_mask = want != np.arange(C.n, dtype=np.uint32)
+        for k in (1, 2):
+            lab_s, e_s = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
+            say(f"[xcd] graph={name} n={C.n} m={C.m} k={k}")
+            for link, find, splice in UF_RULES:
+                for ac in (False, True):
+                    o = G.Options(sample="kout", link=link, find=find, splice=splice, k=k,
+                                  schedule="xcd", atomic_compress=ac)
+                    lab, st = G.cc(dg, options=o, stats=True)
+                    got = G.to_u32(lab)
+                    assert np.array_equal(got, want), (name, k, link, find, splice, ac)
+                    if C.m:
+                        assert st["sampled_edges"] == e_s, (name, k, link)
+                if splice == "splice_atomic":
+                    continue
+                o = G.Options(sample="kout", link=link, find=find, splice=splice, k=k,
+                              schedule="xcd")
+                fu, fv, lab = G.spanning_forest(dg, want_labels=True, options=o)
+                torch.cuda.synchronize()
+                assert np.array_equal(G.to_u32(lab), want), (name, k, link, "forest labels")
+                fu, fv = G.to_u32(fu), G.to_u32(fv)
+                oracle.check_forest(C.n, C.offsets, C.nbrs, fu, fv, want)
+                assert np.array_equal(fu != G.EMPTY, roots_mask), (name, k, link)
+            if C.m:
+                L = oracle.lmax(lab_s, 1024, 1)
+                lab, st = G.cc(dg, options=G.Options(sample="kout", link="rem_cas", k=k,
+                                                     splice="split_one", schedule="xcd"),
+                               stats=True)
+                assert st["lmax"] == L, (name, k)
+                assert st["active_vertices"] == oracle.active_count(C.n, C.offsets, lab_s, L)
+                assert st["finish_edges"] == oracle.active_edges(C.n, C.offsets, lab_s, L)
+
+
 def test_sv_and_label_propagation_all_samplers(cases):
     from paper_2008_11839_amd import gconn as G
     for name, (C, dg, want) in cases.items():
@@ -331,7 +372,7 @@ def test_kout_rem_cas_schedules_agree(cases):
             _, e_s = oracle.sample_kout(C.n, C.offsets, C.nbrs, k)
             for find in ("naive", "split", "halve"):
                 for splice in ("split_one", "halve_one"):
-                    for sched in ("auto", "lane", "step", "pipe", "twopass"):
+                    for sched in ("auto", "lane", "step", "pipe", "twopass", "flat", "xcd"):
                         say(f"[sched] graph={name} k={k} find={find} splice={splice} sched={sched}")
                         o = G.Options(sample="kout", link="rem_cas", find=find, splice=splice,
                                       k=k, schedule=sched)
@@ -350,7 +391,7 @@ def test_hooks_count_is_n_minus_c_with_sampling(cases):
     from paper_2008_11839_amd import gconn as G
     for name, (C, dg, want) in cases.items():
         c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
-        for sched in ("auto", "lane", "step", "pipe", "twopass"):
+        for sched in ("auto", "lane", "step", "pipe", "twopass", "flat", "xcd"):
             lab, st = G.cc(dg, options=G.Options(sample="kout", link="rem_cas", schedule=sched),
                            stats=True)
             assert st["hooks"] == C.n - c, (name, sched)
