@@ -211,7 +211,11 @@ gconn_status gconn_workspace_size(const gconn_graph* g, const gconn_options* opt
  * component.  labels_out doubles as the parent array during the run.
  * workspace: device, >= gconn_workspace_size(g, opt, 0, 1) bytes, 256-byte
  * aligned.  COO input uses the finish phase only (sampling needs CSR).
- * SV, LT and LP iterate with one host synchronisation per round. */
+ * The call returns without waiting, except for the iterative parts whose
+ * length depends on the data: SV, LT and LP run their rounds, and BFS
+ * sampling its levels, eight at a time on the device (each round or level
+ * decides on the device whether to run, and does nothing once the work is
+ * done), with one host check of the stop flag per eight. */
 gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspace,
                       size_t workspace_bytes, const gconn_options* opt, gconn_stats* stats,
                       void* stream);
@@ -351,8 +355,8 @@ gconn_status gconn_autotune(const gconn_graph* graphs, uint32_t num_graphs,
  * Launch-bound callers (small graphs, many repeats) save the per-kernel launch
  * cost.  Only pipelines with no host round trip can be captured: union-find
  * finishes (no SV, LT or LP) with k-out, hook-based or no sampling (BFS checks
- * its frontier on the host), options.validate = 0, no statistics, and phase
- * profiling off -- anything else is GCONN_EUNSUPPORTED.  The caller keeps
+ * its stop flag on the host every eight levels), options.validate = 0, no
+ * statistics, and phase profiling off -- anything else is GCONN_EUNSUPPORTED.  The caller keeps
  * every buffer alive while the handle exists; replays on one handle must not
  * overlap (they share the workspace).  Host-owned handle. */
 typedef struct gconn_exec gconn_exec;

@@ -79,6 +79,10 @@ struct WsLayout {
   size_t kx_dst = 0;  //   second endpoint (same layout)
   size_t kx_root = 0; //   root of the first endpoint's pre-link tree (same layout)
   size_t kx_hdr = 0;  //   records per (chunk, XCD group) (uint32[chunks][8])
+  size_t lrec_src = 0;  // local-first k-out: leaving edges by range and level (uint32)
+  size_t lrec_dst = 0;
+  size_t lrec_hdr = 0;  //   per range: number of records
+  size_t lrec_touched = 0;  //   roots of the united pairs (uint32)
   uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;

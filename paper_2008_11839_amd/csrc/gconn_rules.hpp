@@ -516,6 +516,17 @@ struct Rule {
   // spanning forest records (eu, v).  Union-Rem-CAS with SplitAtomicOne /
   // HalveAtomicOne starts from u; the other rules unite (u, v) when no forest
   // is recorded and (eu, v) when one is.
+  // The union of the input edge (eu, ev) started from a and b, members of
+  // eu's and ev's sets: Union-Rem-CAS with SplitAtomicOne / HalveAtomicOne
+  // unites (a, b) and records (eu, ev) in a spanning forest; the other rules
+  // unite (a, b) when no forest is recorded and (eu, ev) when one is.
+  GCONN_HD static bool unite_pair(const LinkCtx& c, uint32_t a, uint32_t b, uint32_t eu,
+                                  uint32_t ev) {
+    if constexpr (U == kUnionRemCas && S != kSpliceAtomic)
+      return union_rem_cas<F, S>(c, a, b, kEmpty, kEmpty, eu, ev);
+    else if (c.fu) return unite(c, eu, ev);
+    else return unite(c, a, b);
+  }
   GCONN_HD static bool unite_edge(const LinkCtx& c, uint32_t u, uint32_t v, uint32_t pu,
                                   uint32_t pv, uint32_t eu) {
     if constexpr (U == kUnionRemCas && S != kSpliceAtomic)

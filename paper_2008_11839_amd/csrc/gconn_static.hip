@@ -350,13 +350,19 @@ __device__ __forceinline__ uint32_t lds_root(uint32_t* L, uint32_t x) {
 template <typename OffT>
 __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ off,
                                                      const uint32_t* __restrict__ nbrs,
-                                                     uint32_t n, uint32_t k, uint32_t range,
-                                                     uint32_t* P, uint2* res, uint32_t* fu,
-                                                     uint32_t* fv, int local, Ctrl* stats) {
-  extern __shared__ uint32_t L[];  // range entries
+                                                     uint32_t n, uint32_t k, uint32_t shift,
+                                                     uint32_t* P, uint2* res, uint32_t* rsrc,
+                                                     uint32_t* rdst, uint32_t* rcnt,
+                                                     uint32_t* fu, uint32_t* fv, int local,
+                                                     Ctrl* stats) {
+  extern __shared__ uint32_t L[];  // 2^shift entries
+  __shared__ uint32_t nrec;
+  const uint32_t range = 1u << shift;
   const uint64_t lo = (uint64_t)blockIdx.x * range;
   const uint32_t len = (uint32_t)min<uint64_t>(range, n - lo);
+  const uint64_t out = (uint64_t)blockIdx.x * 2 * range;  // this range's record block
   for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) L[i] = i;
+  if (threadIdx.x == 0) nrec = 0;
   __syncthreads();
   unsigned long long sampled = 0, linked = 0;
   for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
@@ -368,8 +374,15 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
     for (uint32_t j = 0; j < t; ++j) {
       const uint32_t w = nbrs[b + j];
       if (!local || w < lo || w >= lo + len) {  // leaves the range: global union pass
-        if (j == 0) r.x = w;
-        else r.y = w;
+        if (local) {
+          const uint32_t at = atomicAdd(&nrec, 1u);
+          rsrc[out + at] = (uint32_t)v;
+          rdst[out + at] = w;
+        } else if (j == 0) {
+          r.x = w;
+        } else {
+          r.y = w;
+        }
         continue;
       }
       // local union of i and w - lo (min-linking, CAS on the larger root)
@@ -390,14 +403,16 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
         c = lds_root(L, low);
       }
     }
-    res[v] = r;
+    if (!local) res[v] = r;
   }
   __syncthreads();
-  if (local)
+  if (local) {
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
       const uint32_t r = lds_root(L, i);
       if (r != i) P[lo + i] = (uint32_t)lo + r;
     }
+    if (threadIdx.x == 0) rcnt[blockIdx.x] = nrec;
+  }
   if (stats) {
     sampled = wave_sum(sampled);
     linked = wave_sum(linked);
@@ -405,6 +420,91 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
       if (sampled) atomicAdd(&stats->stat_sampled, sampled);
       if (linked) atomicAdd(&stats->stat_hooks, linked);
     }
+  }
+}
+
+// Union pass of the local-first k-out over one range's leaving edges (one
+// workgroup per range).  After the local pass every vertex points at its
+// range-local root, so an edge (v, w) joins the sets of a = P[v] and b = P[w];
+// on a mesh most of a range's leaving edges join the same few pairs of local
+// roots.  Each distinct pair is united once: an LDS hash set of the pairs
+// lets only the first lane that brings a pair run the union (when the set is
+// full the lane unites anyway).  Uniting a and b joins the same sets as
+// uniting v and w (P[x] only ever holds members of x's set); a spanning
+// forest records the edge (v, w) itself.  The roots of the united pairs go to
+// the range's block of `touched` (4 * range entries: two per record at most),
+// their number to tcnt[range], for the flattening pass that follows.
+constexpr uint32_t kPairSlots = 16384;  // 128 KB of LDS
+
+template <class R>
+__global__ void __launch_bounds__(1024) k_kout_pairs(const uint32_t* __restrict__ rsrc,
+                                                     const uint32_t* __restrict__ rdst,
+                                                     const uint32_t* __restrict__ rcnt,
+                                                     uint32_t shift, uint32_t* touched,
+                                                     uint32_t* tcnt, LinkCtx lc) {
+  extern __shared__ unsigned long long H[];  // kPairSlots keys, ~0 = empty
+  __shared__ uint32_t nt;
+  for (uint32_t i = threadIdx.x; i < kPairSlots; i += blockDim.x) H[i] = ~0ull;
+  if (threadIdx.x == 0) nt = 0;
+  __syncthreads();
+  const uint64_t tbase = (uint64_t)blockIdx.x * 4 * (1ull << shift);
+  const uint32_t cnt = rcnt[blockIdx.x];
+  const uint64_t base = (uint64_t)blockIdx.x * 2 * (1ull << shift);
+  for (uint32_t j0 = 0; j0 < cnt; j0 += blockDim.x) {
+    const uint32_t j = j0 + threadIdx.x;
+    bool fresh = false;
+    uint32_t v = 0, w = 0, a = 0, b = 0;
+    if (j < cnt) {
+      v = rsrc[base + j];
+      w = rdst[base + j];
+      a = ld(&lc.P[v]);
+      b = ld(&lc.P[w]);
+      if (a != b) {
+        const unsigned long long key = a < b ? ((unsigned long long)a << 32) | b
+                                             : ((unsigned long long)b << 32) | a;
+        uint32_t h = (uint32_t)((key * 0x9e3779b97f4a7c15ull) >> 50) & (kPairSlots - 1);
+        fresh = true;  // unless found, or the probe runs out (then unite anyway)
+        for (int probe = 0; probe < 32; ++probe) {
+          unsigned long long e = ~0ull;
+          if (__hip_atomic_compare_exchange_strong(&H[h], &e, key, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP))
+            break;  // inserted: this lane unites the pair
+          if (e == key) {
+            fresh = false;  // another lane has this pair
+            break;
+          }
+          h = (h + 1) & (kPairSlots - 1);
+        }
+      }
+    }
+    if (fresh) {
+      R::unite_pair(lc, a, b, v, w);
+      const uint32_t at = atomicAdd(&nt, 2u);
+      touched[tbase + at] = a;
+      touched[tbase + at + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) tcnt[blockIdx.x] = nt;
+}
+
+// Every root a pair union touched is pointed at its final root, so the
+// compression that follows reaches any vertex's root in two steps (the
+// vertex's local root, then the final one) instead of walking the chain the
+// range roots formed.  No link runs here: plain reads see every link.
+__global__ void k_kout_touched_flatten(uint32_t* P, const uint32_t* __restrict__ touched,
+                                       const uint32_t* __restrict__ tcnt, uint32_t shift) {
+  const uint32_t cnt = tcnt[blockIdx.x];
+  const uint64_t tbase = (uint64_t)blockIdx.x * 4 * (1ull << shift);
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const uint32_t x = touched[tbase + i];
+    uint32_t r = x, p = P[r];
+    while (p != r) {
+      r = p;
+      p = P[r];
+    }
+    if (r != x) st(&P[x], r);
   }
 }
 
@@ -1970,6 +2070,22 @@ struct Run {
     return GCONN_OK;
   }
 
+  // The pair-union kernel's dynamic LDS (128 KB) is above the 64 KB default
+  // limit: raise it once per rule instantiation.
+  template <class R>
+  static gconn_status pairs_lds_ok() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+      err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_kout_pairs<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(8 * kPairSlots));
+      if (err != hipSuccess) (void)hipGetLastError();
+    });
+    if (err != hipSuccess) return hip_fail(err, "hipFuncSetAttribute(k_kout_pairs)");
+    return GCONN_OK;
+  }
+
   template <typename OffT>
   gconn_status sample_phase() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
@@ -1979,18 +2095,39 @@ struct Run {
     if (o.sample == GCONN_SAMPLE_KOUT) {
       if (kout_local_applies(o)) {
         uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
+        uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.lrec_src);
+        uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.lrec_dst);
+        uint32_t* rcnt = reinterpret_cast<uint32_t*>(ws + L.lrec_hdr);
+        uint32_t* touched = reinterpret_cast<uint32_t*>(ws + L.lrec_touched);
+        uint32_t* tcnt = rcnt + (g.n / kLocalRangeMin + 1);  // after the record counts
+        const bool local = o.kout_local != 0;
         uint32_t range = kLocalRangeMin;
-        GCONN_TRY(local_range<OffT>(&range));
+        if (local) GCONN_TRY(local_range<OffT>(&range));
+        uint32_t shift = 0;
+        while ((1u << shift) < range) ++shift;
         const uint32_t ranges = (uint32_t)((n + range - 1) / range);
-        k_kout_local<OffT><<<ranges, 1024, 4 * range, s>>>(off, g.nbrs, n, o.k, range, P, res,
-                                                           fu, fv, o.kout_local ? 1 : 0, st);
+        k_kout_local<OffT><<<ranges, 1024, 4 * range, s>>>(off, g.nbrs, n, o.k, shift, P, res,
+                                                           rsrc, rdst, rcnt, fu, fv,
+                                                           local ? 1 : 0, st);
         GCONN_LAUNCHED("k_kout_local");
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
           using R = decltype(rule);
-          k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n, link_ctx());
-          GCONN_LAUNCHED("k_kout_residual");
+          if (!local) {
+            k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n,
+                                                                             link_ctx());
+            GCONN_LAUNCHED("k_kout_residual");
+            return GCONN_OK;
+          }
+          GCONN_TRY(pairs_lds_ok<R>());
+          k_kout_pairs<R><<<ranges, 1024, 8 * kPairSlots, s>>>(rsrc, rdst, rcnt, shift, touched,
+                                                              tcnt, link_ctx());
+          GCONN_LAUNCHED("k_kout_pairs");
           return GCONN_OK;
         }));
+        if (local) {
+          k_kout_touched_flatten<<<ranges, 256, 0, s>>>(P, touched, tcnt, shift);
+          GCONN_LAUNCHED("k_kout_touched_flatten");
+        }
       } else if (kout_xcd_applies(o)) {
         uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.kx_src);
         uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.kx_dst);
@@ -2503,7 +2640,16 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
     L.segs = take(8 * L.seg_cap);
   }
   if (needs_claims(o.link)) L.hooks = take(4 * n);
-  if (csr && (kout_prelink_applies(o) || kout_local_applies(o))) L.resid = take(8 * n);
+  if (csr && (kout_prelink_applies(o) || (kout_local_applies(o) && !o.kout_local)))
+    L.resid = take(8 * n);
+  if (csr && kout_local_applies(o) && o.kout_local) {
+    // records: at most two per vertex, in per-range blocks of 2 * range
+    const uint64_t cap = 2 * (n + kLocalRangeMax);
+    L.lrec_src = take(4 * cap);
+    L.lrec_dst = take(4 * cap);
+    L.lrec_hdr = take(8ull * (n / kLocalRangeMin + 1));  // record and touched-root counts
+    L.lrec_touched = take(16 * (n + kLocalRangeMax));  // 4 * range entries per range
+  }
   if (csr && kout_xcd_applies(o)) {
     const uint64_t chunks = (n + kKxChunk - 1) / kKxChunk;
     L.kx_src = take(4 * chunks * kKxCap);
