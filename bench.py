@@ -588,6 +588,76 @@ def batched_bench(G, args) -> dict:
                              "seconds": round(t_cpu, 2), **host_info()}}
 
 
+def samplers_bench(G, args, rmat_dg, rmat_name) -> dict:
+    """The three sampling methods on RMAT-24 and the two percolation grids,
+    with the statistics the paper tabulates per sampler: neighbour entries
+    the sampling reads, the share of the run's time spent sampling, the
+    coverage (vertices in the largest sampled component, L_max's group) and
+    the share of the graph's entries the finish still reads.  Union-Rem-CAS
+    with SplitAtomicOne / FindSplit finishes every run; labels are compared
+    with the oracle's stored labels."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    work = {rmat_name: (None, rmat_name),
+            "grid2d_4096_p0.7": (lambda: graphgen.grid2d(4096, 4096, 0.7, args.seed),
+                                 f"grid2d_4096_p07_s{args.seed}"),
+            "grid3d_256_p0.6": (lambda: graphgen.grid3d(256, 256, 256, 0.6, args.seed),
+                                f"grid3d_256_p06_s{args.seed}")}
+    out = {}
+    for name, (make, gold_name) in work.items():
+        if make is None:
+            dg = rmat_dg
+        else:
+            C = make()
+            dg = G.csr(C.offsets, C.nbrs, C.n)
+            del C
+        n, m = dg.n, dg.m
+        deg = (dg.offsets[1:].to(torch.int64) - dg.offsets[:-1].to(torch.int64))
+        nonisolated = int((deg > 0).sum().item())
+        gold = golden(gold_name)
+        lab = torch.empty(n, dtype=torch.int32, device="cuda")
+        runs = {}
+        for sample in ("kout", "hb", "bfs"):
+            o = G.Options(sample=sample, link="rem_cas", find="split", splice="split_one")
+            ws = G.alloc_workspace(G.workspace_size(dg, o))
+            _, st = G.cc(dg, labels=lab, options=o, workspace=ws, stats=True)
+            ok = labels_sha(G.to_u32(lab)) == gold["labels_sha256"] if gold else None
+            G.cc(dg, labels=lab, options=o, workspace=ws)
+            torch.cuda.synchronize()
+            G.profile_enable(True)
+            G.profile_read(reset=True)
+            ts = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                G.cc(dg, labels=lab, options=o, workspace=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ph = G.profile_read(reset=True)
+            G.profile_enable(False)
+            runs_n = max(ph.pop("runs"), 1)
+            total = sum(v for v in ph.values()) / runs_n
+            sample_ms = (ph["sample_ms"] + ph["lmax_ms"]) / runs_n
+            runs[sample] = {
+                "ms": round(float(np.median(ts)), 4),
+                "sampled_entries": st["sampled_edges"],
+                "sampled_entry_frac": round(st["sampled_edges"] / max(m, 1), 4),
+                "sampling_time_share": round(sample_ms / total, 4) if total > 0 else None,
+                "coverage": round((nonisolated - st["active_vertices"]) / max(n, 1), 4),
+                "finish_entry_frac": round(st["finish_edges"] / max(m, 1), 4),
+                "levels": st["rounds"] if sample == "bfs" else None,
+                "labels_match_oracle_golden": ok}
+            del ws
+        out[name] = {"n": n, "m_directed": m, "runs": runs}
+        del lab
+        if make is not None:
+            del dg
+    return out
+
+
 def ceilings_bench(G, args) -> dict:
     """The chip's random-access ceilings on a 64 MB table (the size of the
     RMAT-24 parent array): random 4-byte cached loads, device-coherent loads
@@ -687,6 +757,17 @@ def other_configs_bench(G, args) -> dict:
                 ex.close()
             res["runs"].append(run)
             del ws
+        # the single-graph autotuner's pick for this graph, against the best
+        # configuration measured above
+        from paper_2008_11839_amd import batch as B
+        choice, times = B.tune_single(dg, reps=3)
+        best = min(res["runs"], key=lambda r: r["ms"])
+        res["autotuned"] = {"choice": choice, "choice_ms_per_run": round(min(times) / 3, 4),
+                            "candidates_ms_per_run": [round(t / 3, 4) for t in times],
+                            "best_measured": {k: v for k, v in best.items()
+                                              if k in ("sample", "link", "find", "splice",
+                                                       "schedule", "kout_local", "lt_variant",
+                                                       "ms")}}
         out[name] = res
         del dg, lab
     return out
@@ -1019,6 +1100,11 @@ def main() -> int:
     # ------------------------------------------------------------ union-find design space
     if not args.no_extras and not args.no_rules:
         result["finish_rules"] = finish_rules_bench(G, args, dg, n, m, gold_sha)
+
+    # ------------------------------------------------------------ sampling methods
+    if not args.no_extras and not args.no_configs:
+        result["samplers"] = samplers_bench(G, args, dg, C.name)
+        log(f"samplers {result['samplers']}")
 
     # ------------------------------------------------------------ ER and grid workloads
     if not args.no_extras and not args.no_configs:

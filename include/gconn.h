@@ -148,8 +148,15 @@ typedef struct gconn_options {
   int32_t kout_random;   /* 0: first k edges; 1: first edge + k-1 uniform picks  */
   int32_t validate;      /* 1: check the graph on the device first (synchronous) */
   int32_t block;         /* threads per workgroup, multiple of 64, <= 1024 (256) */
-  int32_t schedule;      /* k-out kernel shape: 0 persistent lanes with the next
-                            vertex's row prefetched (default), 1 one lane per
+  int32_t schedule;      /* k-out kernel shape: 0 automatic (default): for first
+                            k <= 2 a probe of 4096 seeded vertices decides on
+                            the device -- the local-first passes (kout_local)
+                            when at least a quarter of the sampled edges stay
+                            inside their vertex's id range and the graph spans
+                            at least 64 ranges (meshes and other graphs whose
+                            ids follow their geometry), else persistent lanes
+                            with the next vertex's row prefetched (the only
+                            choice for k > 2 or random picks); 1 one lane per
                             vertex, 2 lane-refill step machine (Union-Rem-CAS,
                             first-k, uint32 offsets; else as 0), 3 two-stage
                             pipeline: the next vertex's neighbour parents
@@ -163,7 +170,12 @@ typedef struct gconn_options {
                             then a pass that points every vertex at its
                             pre-link tree's root, then the union pass over
                             the remaining sampled edges, starting from roots
-                            (first k <= 2; else as 0)                      (0) */
+                            (first k <= 2; else as 0), 6 XCD-bucketed: the
+                            pre-link and flattening, then the remaining
+                            sampled edges grouped by the XCD whose share of
+                            the ids holds their second endpoint and united by
+                            workgroups running on that XCD (first k <= 2;
+                            else as 0)                                     (0) */
   int32_t atomic_compress; /* path-compression and splice writes (FindSplit,
                             FindHalve, SplitAtomicOne, HalveAtomicOne, the
                             Union-Early splice): 1 CAS as in the atomic rules,
@@ -178,11 +190,13 @@ typedef struct gconn_options {
                             Same partition either way.                     (0) */
   int32_t kout_local;    /* first-k k-out with k <= 2: 1 unites, in LDS, the
                             sampled edges whose endpoints both lie in the same
-                            8192-vertex id range (one workgroup per range), and
-                            sends only the edges leaving a range through the
-                            union rule -- for graphs whose ids are local, such
-                            as grids and meshes.  Same partition.  Overrides
-                            kout_prelink.                                   (0) */
+                            id range (one workgroup per range; the largest
+                            power of two up to 32768 vertices whose parents
+                            fit the device's LDS), then unites each distinct
+                            pair of range-local roots that the edges leaving a
+                            range join, once -- for graphs whose ids are
+                            local, such as grids and meshes.  Same partition.
+                            Overrides kout_prelink.                         (0) */
 } gconn_options;
 
 /* Counters filled when a stats pointer is passed (the call then synchronises
@@ -228,8 +242,10 @@ gconn_status gconn_cc(const gconn_graph* g, uint32_t* labels_out, void* workspac
  * device, from the first use until the process ends.  The call allocates
  * nothing (no hipMalloc, no hipFree, no allocating library routine).
  * Returns GCONN_ENOMEM, before enqueuing anything, when gconn_workspace_size
- * for this graph and these options exceeds the scratch size (about n <= 7.5M
- * vertices for the default k-out pipeline), and GCONN_EUNSUPPORTED while phase
+ * for this graph and these options exceeds the scratch size (with 16 entries
+ * per vertex: about n <= 2.7M vertices for the default automatic k-out
+ * schedule, which keeps room for the local-first passes, and about n <= 8.1M
+ * with schedule 1), and GCONN_EUNSUPPORTED while phase
  * profiling is on.  Every call on one device shares that device's scratch
  * array and leaves it holding its own intermediate state (each run clears what
  * it needs with kernels): calls that may overlap on one device -- on
@@ -314,11 +330,13 @@ typedef struct gconn_batch {
 } gconn_batch;
 
 typedef struct gconn_class_options {
-  int32_t sample;    /* GCONN_SAMPLE_NONE or GCONN_SAMPLE_KOUT (first k edges)      */
+  int32_t sample;    /* GCONN_SAMPLE_NONE, GCONN_SAMPLE_KOUT (first k edges) or
+                        GCONN_SAMPLE_HB (hook to the first neighbour, then the
+                        first k edges of the vertices that stayed roots)         */
   int32_t link;      /* GCONN_LINK_ASYNC, GCONN_LINK_REM_CAS or GCONN_LINK_EARLY    */
   int32_t find;      /* GCONN_FIND_NAIVE, _SPLIT or _HALVE                          */
   int32_t splice;    /* GCONN_SPLICE_* (Union-Rem-CAS)                              */
-  uint32_t k;        /* k-out edges per vertex (1..64)                              */
+  uint32_t k;        /* k-out edges per vertex, or hook-based N (1..64)             */
   uint32_t reserved;
 } gconn_class_options;
 

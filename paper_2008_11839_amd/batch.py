@@ -31,6 +31,29 @@ CANDIDATES = [
     dict(sample="none", link="async", find="split"),
     dict(sample="none", link="async", find="halve"),
     dict(sample="kout", link="early", find="split"),
+    dict(sample="hb", link="rem_cas", find="split", splice="split_one", hb_n=4),
+    dict(sample="hb", link="async", find="halve", hb_n=4),
+    dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic"),
+]
+
+
+# Candidates for one graph on its own (gconn_cc): the whole design space the
+# single-graph pipeline offers -- the automatic k-out schedule (local-first
+# passes on graphs whose ids follow their geometry), hook-based and BFS
+# sampling, no sampling, and the round-based finishes for high-diameter
+# graphs.
+SINGLE_CANDIDATES = [
+    dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic"),
+    dict(sample="kout", link="rem_cas", find="split", splice="split_one"),
+    dict(sample="kout", link="rem_cas", find="naive", splice="split_one"),
+    dict(sample="kout", link="async", find="halve"),
+    dict(sample="hb", link="rem_cas", find="split", splice="split_one"),
+    dict(sample="hb", link="async", find="halve"),
+    dict(sample="bfs", link="rem_cas", find="split", splice="split_one"),
+    dict(sample="none", link="rem_cas", find="split", splice="split_one"),
+    dict(sample="none", link="async", find="halve"),
+    dict(sample="kout", link="sv"),
+    dict(sample="kout", link="lt", lt_variant="PRF"),
 ]
 
 
@@ -113,7 +136,8 @@ def class_options(spec: dict) -> G._ClassOptions:
     c.link = G.LINK[spec.get("link", "async")]
     c.find = G.FIND[spec.get("find", "split")]
     c.splice = G.SPLICE[spec.get("splice", "split_one")]
-    c.k = spec.get("k", 2)
+    # hook-based classes carry N (the edges of step 2) in k
+    c.k = spec.get("hb_n", 4) if spec.get("sample") == "hb" else spec.get("k", 2)
     return c
 
 
@@ -168,6 +192,13 @@ def autotune(device_graphs: list, candidates=CANDIDATES, reps: int = 3, stream=N
                                 scratch.data_ptr(), ws.data_ptr(), ws.numel(), G._stream(stream),
                                 ctypes.byref(best), times))
     return best.value, list(times)
+
+
+def tune_single(device_graph, candidates=SINGLE_CANDIDATES, reps: int = 3, stream=None):
+    """The fastest option set for one graph: (options dict, times in ms per
+    candidate, in candidate order), timed with gconn_autotune."""
+    best, times = autotune([device_graph], candidates, reps, stream)
+    return dict(candidates[best]), times
 
 
 class Autotuner:

@@ -49,9 +49,9 @@ __device__ __forceinline__ bool unite_by_id(uint32_t rid, const LinkCtx& c, uint
 }
 
 struct BatchClass {
-  uint32_t sample;  // 0 none, 1 k-out
+  uint32_t sample;  // 0 none, 1 k-out, 2 hook-based
   uint32_t rule;    // rule id
-  uint32_t k;
+  uint32_t k;       // k-out: edges per vertex; hook-based: N, the edges of step 2
   uint32_t pad;
 };
 struct BatchClasses {
@@ -90,13 +90,47 @@ __global__ void k_batch_sample(const uint64_t* __restrict__ off, const uint32_t*
     if (!bc.sample) continue;  // uniform over the wave: one graph per tile
     const uint64_t v = base + lane();
     const uint64_t b = off[v], deg = off[v + 1] - b;
-    const uint32_t take = (uint32_t)(deg < bc.k ? deg : bc.k);
+    uint32_t take = (uint32_t)(deg < bc.k ? deg : bc.k);
+    // hook-based step 2: only the vertices step 1 left as roots (degree 0, or
+    // first neighbour not smaller -- decided from the graph, not from P)
+    if (bc.sample == 2 && (deg == 0 || nbrs[b] < v)) take = 0;
     for (uint32_t j = 0; j < take; ++j) unite_by_id(bc.rule, lc, (uint32_t)v, nbrs[b + j]);
     sampled += take;
   }
   if (stats) {
     sampled = wave_sum(sampled);
     if (lane() == 0 && sampled) atomicAdd(&stats->stat_sampled, sampled);
+  }
+}
+
+// Hook-based sampling, step 1, for the tiles of hook-based classes (Sampling
+// Algorithms, HB): P[v] = min(v, first neighbour).  Every vertex is still a
+// root and its lane the only writer of its slot, so this is a plain store.
+__global__ void k_batch_hb1(const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbrs,
+                            uint32_t n, const uint32_t* __restrict__ tile_graph,
+                            const uint8_t* __restrict__ graph_class, BatchClasses cl, uint32_t* P,
+                            Ctrl* stats) {
+  unsigned long long took = 0, linked = 0;
+  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
+    if (class_of(cl, graph_class, tile_graph[base >> 6]).sample != 2) continue;  // per tile
+    const uint64_t v = base + lane();
+    const uint64_t b = off[v];
+    if (off[v + 1] > b) {
+      ++took;
+      const uint32_t w = nbrs[b];
+      if (w < v) {
+        P[v] = w;
+        ++linked;
+      }
+    }
+  }
+  if (stats) {
+    took = wave_sum(took);
+    linked = wave_sum(linked);
+    if (lane() == 0) {
+      if (took) atomicAdd(&stats->stat_sampled, took);
+      if (linked) atomicAdd(&stats->stat_hooks, linked);
+    }
   }
 }
 
@@ -315,11 +349,12 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
   std::memset(&cl, 0, sizeof(cl));
   for (uint32_t i = 0; i < num_classes; ++i) {
     const gconn_class_options& c = classes[i];
-    if (c.sample != GCONN_SAMPLE_NONE && c.sample != GCONN_SAMPLE_KOUT)
-      return fail(GCONN_EUNSUPPORTED, "batched classes sample with k-out or not at all");
-    if (c.sample == GCONN_SAMPLE_KOUT && (c.k < 1 || c.k > 64))
-      return fail(GCONN_EINVAL, "class k must be in [1, 64]");
-    cl.c[i].sample = c.sample == GCONN_SAMPLE_KOUT;
+    if (c.sample != GCONN_SAMPLE_NONE && c.sample != GCONN_SAMPLE_KOUT &&
+        c.sample != GCONN_SAMPLE_HB)
+      return fail(GCONN_EUNSUPPORTED, "batched classes sample with k-out, hook-based or not at all");
+    if (c.sample != GCONN_SAMPLE_NONE && (c.k < 1 || c.k > 64))
+      return fail(GCONN_EINVAL, "class k (k-out edges, or hook-based N) must be in [1, 64]");
+    cl.c[i].sample = c.sample == GCONN_SAMPLE_KOUT ? 1u : c.sample == GCONN_SAMPLE_HB ? 2u : 0u;
     cl.c[i].k = c.k;
     GCONN_TRY(rule_id(c, &cl.c[i].rule));
   }
@@ -355,6 +390,13 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
   k_batch_tiles<<<grid_for(G, block), block, 0, s>>>(b->vbase, G, tiles);
   GCONN_LAUNCHED("k_batch_tiles");
   if (n > 0 && b->m > 0) {
+    bool any_hb = false;
+    for (uint32_t i = 0; i < num_classes; ++i) any_hb = any_hb || cl.c[i].sample == 2;
+    if (any_hb) {
+      k_batch_hb1<<<std::min<uint32_t>(grid_for(n, block), 8192), block, 0, s>>>(
+          b->offsets, b->nbrs, n, tiles, b->graph_class, cl, P, st);
+      GCONN_LAUNCHED("k_batch_hb1");
+    }
     const uint32_t sgrid = persistent_grid(k_batch_sample, block);
     k_batch_sample<<<sgrid, block, 0, s>>>(b->offsets, b->nbrs, n, tiles, b->graph_class, cl, lc, st);
     GCONN_LAUNCHED("k_batch_sample");

@@ -148,7 +148,8 @@ __global__ void k_sample_kout(const OffT* __restrict__ off, const uint32_t* __re
 template <class R, typename OffT>
 __global__ void k_sample_kout_pf(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
                                  uint32_t n, uint32_t k, int random, uint64_t seed, LinkCtx lc,
-                                 Ctrl* stats) {
+                                 Ctrl* stats, const Ctrl* gate) {
+  if (gate && gate->kout_mode != 0) return;  // the automatic schedule chose the local passes
   const uint64_t T = wave_stride();
   uint64_t v = gtid();
   // row of v: start b, degree d, first two sampled neighbours
@@ -354,9 +355,10 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
                                                      uint32_t* P, uint2* res, uint32_t* rsrc,
                                                      uint32_t* rdst, uint32_t* rcnt,
                                                      uint32_t* fu, uint32_t* fv, int local,
-                                                     Ctrl* stats) {
+                                                     Ctrl* stats, const Ctrl* gate) {
   extern __shared__ uint32_t L[];  // 2^shift entries
   __shared__ uint32_t nrec;
+  if (gate && gate->kout_mode != 1) return;  // the automatic schedule chose the one-pass kernel
   const uint32_t range = 1u << shift;
   const uint64_t lo = (uint64_t)blockIdx.x * range;
   const uint32_t len = (uint32_t)min<uint64_t>(range, n - lo);
@@ -365,45 +367,63 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
   if (threadIdx.x == 0) nrec = 0;
   __syncthreads();
   unsigned long long sampled = 0, linked = 0;
-  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-    const uint64_t v = lo + i;
-    const uint64_t b = off[v], d = (uint64_t)off[v + 1] - b;
-    const uint32_t t = (uint32_t)(d < k ? d : k);
-    sampled += t;
-    uint2 r = make_uint2(kEmpty, kEmpty);
-    for (uint32_t j = 0; j < t; ++j) {
-      const uint32_t w = nbrs[b + j];
-      if (!local || w < lo || w >= lo + len) {  // leaves the range: global union pass
-        if (local) {
-          const uint32_t at = atomicAdd(&nrec, 1u);
-          rsrc[out + at] = (uint32_t)v;
-          rdst[out + at] = w;
-        } else if (j == 0) {
-          r.x = w;
-        } else {
-          r.y = w;
-        }
-        continue;
-      }
-      // local union of i and w - lo (min-linking, CAS on the larger root)
-      uint32_t a = lds_root(L, i), c = lds_root(L, (uint32_t)(w - lo));
-      while (a != c) {
-        const uint32_t hi = a > c ? a : c, low = a > c ? c : a;
-        uint32_t e = hi;
-        if (__hip_atomic_compare_exchange_strong(&L[hi], &e, low, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-          ++linked;
-          if (fu) {
-            fu[lo + hi] = (uint32_t)v;
-            fv[lo + hi] = w;
-          }
-          break;
-        }
-        a = lds_root(L, e);
-        c = lds_root(L, low);
-      }
+  // Each lane takes four consecutive vertices per step and loads their row
+  // bounds and leading neighbours (up to eight loads) before any union runs.
+  for (uint32_t i0 = 4 * threadIdx.x; i0 < len; i0 += 4 * blockDim.x) {
+    uint64_t o[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] = i0 + j <= len ? (uint64_t)off[lo + i0 + j] : 0;
+    uint32_t wv[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t d = i0 + j < len ? o[j + 1] - o[j] : 0;
+      wv[2 * j] = d > 0 ? nbrs[o[j]] : kEmpty;
+      wv[2 * j + 1] = (d > 1 && k > 1) ? nbrs[o[j] + 1] : kEmpty;
     }
-    if (!local) res[v] = r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t i = i0 + j;
+      if (i >= len) break;
+      const uint64_t v = lo + i;
+      const uint64_t d = o[j + 1] - o[j];
+      const uint32_t t = (uint32_t)(d < k ? d : k);
+      sampled += t;
+      uint2 r = make_uint2(kEmpty, kEmpty);
+      for (uint32_t e2 = 0; e2 < t; ++e2) {
+        const uint32_t w = e2 == 0 ? wv[2 * j] : wv[2 * j + 1];
+        if (!local || w < lo || w >= lo + len) {  // leaves the range: global union pass
+          if (local) {
+            const uint32_t at = atomicAdd(&nrec, 1u);
+            rsrc[out + at] = (uint32_t)v;
+            rdst[out + at] = w;
+          } else if (e2 == 0) {
+            r.x = w;
+          } else {
+            r.y = w;
+          }
+          continue;
+        }
+        // local union of i and w - lo (min-linking, CAS on the larger root)
+        uint32_t a = lds_root(L, i), c = lds_root(L, (uint32_t)(w - lo));
+        while (a != c) {
+          const uint32_t hi = a > c ? a : c, low = a > c ? c : a;
+          uint32_t e = hi;
+          if (__hip_atomic_compare_exchange_strong(&L[hi], &e, low, __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            ++linked;
+            if (fu) {
+              fu[lo + hi] = (uint32_t)v;
+              fv[lo + hi] = w;
+            }
+            break;
+          }
+          a = lds_root(L, e);
+          c = lds_root(L, low);
+        }
+      }
+      if (!local) res[v] = r;
+    }
   }
   __syncthreads();
   if (local) {
@@ -431,23 +451,21 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
 // lets only the first lane that brings a pair run the union (when the set is
 // full the lane unites anyway).  Uniting a and b joins the same sets as
 // uniting v and w (P[x] only ever holds members of x's set); a spanning
-// forest records the edge (v, w) itself.  The roots of the united pairs go to
-// the range's block of `touched` (4 * range entries: two per record at most),
-// their number to tcnt[range], for the flattening pass that follows.
+// forest records the edge (v, w) itself.  (Pointing the united roots at their
+// final roots afterwards was measured slower: the compression pass that
+// follows reaches the roots anyway.)
 constexpr uint32_t kPairSlots = 16384;  // 128 KB of LDS
 
 template <class R>
 __global__ void __launch_bounds__(1024) k_kout_pairs(const uint32_t* __restrict__ rsrc,
                                                      const uint32_t* __restrict__ rdst,
                                                      const uint32_t* __restrict__ rcnt,
-                                                     uint32_t shift, uint32_t* touched,
-                                                     uint32_t* tcnt, LinkCtx lc) {
+                                                     uint32_t shift, LinkCtx lc,
+                                                     const Ctrl* gate) {
   extern __shared__ unsigned long long H[];  // kPairSlots keys, ~0 = empty
-  __shared__ uint32_t nt;
+  if (gate && gate->kout_mode != 1) return;
   for (uint32_t i = threadIdx.x; i < kPairSlots; i += blockDim.x) H[i] = ~0ull;
-  if (threadIdx.x == 0) nt = 0;
   __syncthreads();
-  const uint64_t tbase = (uint64_t)blockIdx.x * 4 * (1ull << shift);
   const uint32_t cnt = rcnt[blockIdx.x];
   const uint64_t base = (uint64_t)blockIdx.x * 2 * (1ull << shift);
   for (uint32_t j0 = 0; j0 < cnt; j0 += blockDim.x) {
@@ -478,33 +496,63 @@ __global__ void __launch_bounds__(1024) k_kout_pairs(const uint32_t* __restrict_
         }
       }
     }
-    if (fresh) {
-      R::unite_pair(lc, a, b, v, w);
-      const uint32_t at = atomicAdd(&nt, 2u);
-      touched[tbase + at] = a;
-      touched[tbase + at + 1] = b;
-    }
+    if (fresh) R::unite_pair(lc, a, b, v, w);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) tcnt[blockIdx.x] = nt;
 }
 
-// Every root a pair union touched is pointed at its final root, so the
-// compression that follows reaches any vertex's root in two steps (the
-// vertex's local root, then the final one) instead of walking the chain the
-// range roots formed.  No link runs here: plain reads see every link.
-__global__ void k_kout_touched_flatten(uint32_t* P, const uint32_t* __restrict__ touched,
-                                       const uint32_t* __restrict__ tcnt, uint32_t shift) {
-  const uint32_t cnt = tcnt[blockIdx.x];
-  const uint64_t tbase = (uint64_t)blockIdx.x * 4 * (1ull << shift);
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const uint32_t x = touched[tbase + i];
-    uint32_t r = x, p = P[r];
-    while (p != r) {
-      r = p;
-      p = P[r];
+// Locality probe of the automatic k-out schedule: kProbeBlocks x 256 seeded
+// vertices count their sampled edges and how many stay inside the vertex's
+// own local-first id range; the last block to finish decides.  The local
+// passes run when at least a quarter of the sampled edges are range-local --
+// meshes and other graphs whose ids follow their geometry -- and the
+// one-pass kernel runs otherwise (a scrambled RMAT graph keeps ~range/n of
+// them), provided the graph spans at least kProbeMinRanges ranges (one
+// workgroup each: fewer cannot fill the chip).  Exact either way: the choice
+// only picks the schedule.
+constexpr uint32_t kProbeBlocks = 16;
+constexpr uint32_t kProbeMinRanges = 64;
+
+template <typename OffT>
+__global__ void __launch_bounds__(256) k_kout_probe(const OffT* __restrict__ off,
+                                                    const uint32_t* __restrict__ nbrs, uint32_t n,
+                                                    uint32_t k, uint32_t shift, uint64_t seed,
+                                                    Ctrl* c) {
+  __shared__ uint32_t s_loc, s_tot, s_last;
+  if (threadIdx.x == 0) s_loc = s_tot = 0;
+  __syncthreads();
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t v = (uint32_t)(((splitmix64_at(seed, j) >> 32) * (uint64_t)n) >> 32);
+  uint32_t loc = 0, tot = 0;
+  if (v < n) {
+    const uint64_t b = off[v], d = (uint64_t)off[v + 1] - b;
+    const uint32_t t = (uint32_t)(d < k ? d : k);
+    for (uint32_t i = 0; i < t; ++i) {
+      ++tot;
+      loc += (nbrs[b + i] >> shift) == (v >> shift);
     }
-    if (r != x) st(&P[x], r);
+  }
+  if (tot) {
+    atomicAdd(&s_loc, loc);
+    atomicAdd(&s_tot, tot);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c->probe_part[2 * blockIdx.x] = s_loc;
+    c->probe_part[2 * blockIdx.x + 1] = s_tot;
+    __threadfence();
+    s_last = atomicAdd(&c->probe_done, 1u) == kProbeBlocks - 1;
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    __threadfence();
+    uint64_t L = 0, T = 0;
+    for (uint32_t b = 0; b < kProbeBlocks; ++b) {
+      L += __hip_atomic_load(&c->probe_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      T += __hip_atomic_load(&c->probe_part[2 * b + 1], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t ranges = ((uint64_t)n + (1ull << shift) - 1) >> shift;
+    c->kout_mode = (T > 0 && 4 * L >= T && ranges >= kProbeMinRanges) ? 1u : 0u;
   }
 }
 
@@ -1863,6 +1911,12 @@ bool kout_flat_applies(const gconn_options& o) {
   return !kout_local_applies(o) && o.schedule == 5 && o.sample == GCONN_SAMPLE_KOUT &&
          !o.kout_random && o.k <= 2;
 }
+// The automatic k-out schedule (schedule 0, first k <= 2): a locality probe
+// on the device chooses between the local-first passes and the one-pass kernel.
+bool kout_auto_local_applies(const gconn_options& o) {
+  return o.schedule == 0 && o.sample == GCONN_SAMPLE_KOUT && !o.kout_random && o.k <= 2 &&
+         !o.kout_local && !o.kout_prelink;
+}
 // The XCD-bucketed k-out passes (k_kx_stream, k_kx_flatten, k_kx_unite).
 bool kout_xcd_applies(const gconn_options& o) {
   return !kout_local_applies(o) && o.schedule == 6 && o.sample == GCONN_SAMPLE_KOUT &&
@@ -2086,6 +2140,44 @@ struct Run {
     return GCONN_OK;
   }
 
+  // The slot-array k-out passes: local-first (LDS pass, then pair unions over
+  // the leaving edges) or, with local == false,
+  // the plain two-pass schedule.  gate (nullable): the automatic schedule's
+  // control block; the local passes then run only if its probe chose them.
+  template <typename OffT>
+  gconn_status local_passes(bool local, const Ctrl* gate) {
+    const OffT* off = static_cast<const OffT*>(g.offsets);
+    const uint32_t n = g.n;
+    Ctrl* st = want_stats ? ctrl : nullptr;
+    uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
+    uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.lrec_src);
+    uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.lrec_dst);
+    uint32_t* rcnt = reinterpret_cast<uint32_t*>(ws + L.lrec_hdr);
+    uint32_t range = kLocalRangeMin;
+    if (local) GCONN_TRY(local_range<OffT>(&range));
+    uint32_t shift = 0;
+    while ((1u << shift) < range) ++shift;
+    const uint32_t ranges = (uint32_t)((n + range - 1) / range);
+    k_kout_local<OffT><<<ranges, 1024, 4 * range, s>>>(off, g.nbrs, n, o.k, shift, P, res, rsrc,
+                                                       rdst, rcnt, fu, fv, local ? 1 : 0, st,
+                                                       gate);
+    GCONN_LAUNCHED("k_kout_local");
+    GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
+      using R = decltype(rule);
+      if (!local) {
+        k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n, link_ctx());
+        GCONN_LAUNCHED("k_kout_residual");
+        return GCONN_OK;
+      }
+      GCONN_TRY(pairs_lds_ok<R>());
+      k_kout_pairs<R><<<ranges, 1024, 8 * kPairSlots, s>>>(rsrc, rdst, rcnt, shift, link_ctx(),
+                                                          gate);
+      GCONN_LAUNCHED("k_kout_pairs");
+      return GCONN_OK;
+    }));
+    return GCONN_OK;
+  }
+
   template <typename OffT>
   gconn_status sample_phase() {
     const OffT* off = static_cast<const OffT*>(g.offsets);
@@ -2094,40 +2186,7 @@ struct Run {
     GCONN_TRY(prof_mark(kPhaseSample, true, s));
     if (o.sample == GCONN_SAMPLE_KOUT) {
       if (kout_local_applies(o)) {
-        uint2* res = reinterpret_cast<uint2*>(ws + L.resid);
-        uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.lrec_src);
-        uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.lrec_dst);
-        uint32_t* rcnt = reinterpret_cast<uint32_t*>(ws + L.lrec_hdr);
-        uint32_t* touched = reinterpret_cast<uint32_t*>(ws + L.lrec_touched);
-        uint32_t* tcnt = rcnt + (g.n / kLocalRangeMin + 1);  // after the record counts
-        const bool local = o.kout_local != 0;
-        uint32_t range = kLocalRangeMin;
-        if (local) GCONN_TRY(local_range<OffT>(&range));
-        uint32_t shift = 0;
-        while ((1u << shift) < range) ++shift;
-        const uint32_t ranges = (uint32_t)((n + range - 1) / range);
-        k_kout_local<OffT><<<ranges, 1024, 4 * range, s>>>(off, g.nbrs, n, o.k, shift, P, res,
-                                                           rsrc, rdst, rcnt, fu, fv,
-                                                           local ? 1 : 0, st);
-        GCONN_LAUNCHED("k_kout_local");
-        GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
-          using R = decltype(rule);
-          if (!local) {
-            k_kout_residual<R><<<contention_grid(gridN(n), n), block, 0, s>>>(res, n,
-                                                                             link_ctx());
-            GCONN_LAUNCHED("k_kout_residual");
-            return GCONN_OK;
-          }
-          GCONN_TRY(pairs_lds_ok<R>());
-          k_kout_pairs<R><<<ranges, 1024, 8 * kPairSlots, s>>>(rsrc, rdst, rcnt, shift, touched,
-                                                              tcnt, link_ctx());
-          GCONN_LAUNCHED("k_kout_pairs");
-          return GCONN_OK;
-        }));
-        if (local) {
-          k_kout_touched_flatten<<<ranges, 256, 0, s>>>(P, touched, tcnt, shift);
-          GCONN_LAUNCHED("k_kout_touched_flatten");
-        }
+        GCONN_TRY(local_passes<OffT>(o.kout_local != 0, nullptr));
       } else if (kout_xcd_applies(o)) {
         uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.kx_src);
         uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.kx_dst);
@@ -2204,11 +2263,25 @@ struct Run {
           return GCONN_OK;
         }));
       } else {
+        // Automatic schedule: the locality probe picks the local-first passes
+        // or the one-pass kernel on the device; the other side returns at once.
+        const Ctrl* gate = nullptr;
+        if (kout_auto_local_applies(o)) {
+          uint32_t range = kLocalRangeMin, shift = 0;
+          GCONN_TRY(local_range<OffT>(&range));
+          while ((1u << shift) < range) ++shift;
+          k_kout_probe<OffT><<<kProbeBlocks, 256, 0, s>>>(off, g.nbrs, n, o.k, shift,
+                                                          o.seed ^ 0x70726f6265ull, ctrl);
+          GCONN_LAUNCHED("k_kout_probe");
+          gate = ctrl;
+          GCONN_TRY(local_passes<OffT>(true, gate));
+        }
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
           using R = decltype(rule);
           const uint32_t grid = contention_grid(persistent_grid(k_sample_kout_pf<R, OffT>, block), n);
           k_sample_kout_pf<R, OffT><<<grid, block, 0, s>>>(off, g.nbrs, n, o.k, o.kout_random,
-                                                           o.seed ^ 0x6b6f7574ull, link_ctx(), st);
+                                                           o.seed ^ 0x6b6f7574ull, link_ctx(), st,
+                                                           gate);
           GCONN_LAUNCHED("k_sample_kout_pf");
           return GCONN_OK;
         }));
@@ -2642,13 +2715,12 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
   if (needs_claims(o.link)) L.hooks = take(4 * n);
   if (csr && (kout_prelink_applies(o) || (kout_local_applies(o) && !o.kout_local)))
     L.resid = take(8 * n);
-  if (csr && kout_local_applies(o) && o.kout_local) {
+  if (csr && ((kout_local_applies(o) && o.kout_local) || kout_auto_local_applies(o))) {
     // records: at most two per vertex, in per-range blocks of 2 * range
     const uint64_t cap = 2 * (n + kLocalRangeMax);
     L.lrec_src = take(4 * cap);
     L.lrec_dst = take(4 * cap);
-    L.lrec_hdr = take(8ull * (n / kLocalRangeMin + 1));  // record and touched-root counts
-    L.lrec_touched = take(16 * (n + kLocalRangeMax));  // 4 * range entries per range
+    L.lrec_hdr = take(4ull * (n / kLocalRangeMin + 1));  // record counts
   }
   if (csr && kout_xcd_applies(o)) {
     const uint64_t chunks = (n + kKxChunk - 1) / kKxChunk;

@@ -82,8 +82,13 @@ def test_workspace_sizes_scale_with_the_plan():
     assert hooks - base >= 4 * n
     st, sv = _ws(_graph(n, m), link="sv")
     assert sv - base >= 4 * n + 8 * m             # prev + materialised edges
+    st, none = _ws(_graph(n, m), sample="none")
     st, bfs = _ws(_graph(n, m), sample="bfs")
-    assert bfs - base >= 8 * n                    # two queues
+    assert bfs - none >= 8 * n                    # two queues
+    # the automatic k-out schedule keeps room for the local-first records
+    # (two per vertex, both endpoints); the one-pass kernel alone needs none
+    st, lane = _ws(_graph(n, m), schedule="lane")
+    assert base - lane >= 16 * n
     st, coo = _ws(_graph(n, m, fmt=1))
     assert coo < 4096                             # COO union-find needs control only
 
@@ -147,7 +152,7 @@ def test_jtb_options_and_workspace():
     assert status(link="async", find="two_try_split") == -7
     # the words (8 bytes per vertex) and the root array (4) are in the plan
     n, m = 1 << 20, 1 << 22
-    st, base = _ws(_graph(n, m), link="async")
+    st, base = _ws(_graph(n, m), link="async", schedule="lane")
     st2, jtb = _ws(_graph(n, m), link="jtb", find="naive")
     assert st == 0 and st2 == 0 and jtb - base >= 12 * n
     # the incremental handle keeps the words in its workspace

@@ -40,6 +40,10 @@ CLASS_SETS = [
     [dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic", k=2),
      dict(sample="none", link="rem_cas", find="halve", splice="splice_atomic"),
      dict(sample="kout", link="rem_cas", find="naive", splice="splice_atomic", k=3)],
+    [dict(sample="hb", link="rem_cas", find="split", splice="split_one", hb_n=4),
+     dict(sample="hb", link="async", find="halve", hb_n=2),
+     dict(sample="kout", link="rem_cas", find="split", splice="split_one", k=2),
+     dict(sample="none", link="early", find="split")],
 ]
 
 
@@ -76,6 +80,24 @@ def test_batch_labels_match_oracle_per_graph(batch_case):
             _check(hb, gs, want, lab)
             c_total = sum(int((w == np.arange(len(w), dtype=np.uint32)).sum()) for w in want)
             assert st["hooks"] == sum(g.n for g in gs) - c_total
+
+
+@pytest.mark.parametrize("hb_n", [1, 4])
+def test_batch_hook_based_sampled_count(batch_case, hb_n):
+    """A batch whose graphs all sample hook-based: per-graph labels equal the
+    oracle's, and the sampled entries add up to the oracle's count of the
+    same sampler over every graph."""
+    import torch
+    from paper_2008_11839_amd import batch as B
+    gs, want = batch_case
+    hb = B.concat(gs)
+    db = B.upload(hb)
+    lab, st = B.cc_batch(db, [dict(sample="hb", link="rem_cas", find="split", hb_n=hb_n)],
+                         stats=True)
+    torch.cuda.synchronize()
+    _check(hb, gs, want, lab)
+    assert st["sampled_edges"] == sum(oracle.sample_hb(g.n, g.offsets, g.nbrs, hb_n)[1]
+                                      for g in gs)
 
 
 def test_batch_single_graph_equals_gconn_cc(batch_case):
@@ -130,6 +152,6 @@ def test_batch_rejects_bad_layouts(batch_case):
         B.cc_batch(db, [dict()])
     db = B.upload(B.concat(gs[:3]))
     with pytest.raises(G.GconnError):
-        B.cc_batch(db, [dict(sample="hb")])
+        B.cc_batch(db, [dict(sample="bfs")])
     with pytest.raises(G.GconnError):
         B.cc_batch(db, [dict(link="sv")])

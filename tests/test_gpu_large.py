@@ -109,3 +109,50 @@ def test_rmat22_incremental(rmat22, ac):
         torch.cuda.synchronize()
         assert np.array_equal(got, want), (link, find, ac)
         inc.close()
+
+
+@pytest.fixture(scope="module")
+def grid3m(gpu_available):
+    """A 2048 x 1536 bond-percolation grid at p = 0.65 (3.1 M vertices): ids
+    follow the geometry, so the automatic k-out schedule takes the
+    local-first passes (at least 64 id ranges, most sampled edges inside one)."""
+    from paper_2008_11839_amd import gconn as G
+    C = graphgen.grid2d(2048, 1536, 0.65, 5)
+    want = oracle.cc(C.n, C.offsets, C.nbrs)
+    return C, G.csr(C.offsets, C.nbrs, C.n), want
+
+
+@pytest.mark.parametrize("cfg", [dict(link="rem_cas", find="split", splice="splice_atomic"),
+                                 dict(link="rem_cas", find="split", splice="split_one"),
+                                 dict(link="rem_cas", find="naive", splice="split_one"),
+                                 dict(link="async", find="halve"),
+                                 dict(link="early", find="split"),
+                                 dict(link="sv")],
+                         ids=lambda c: "-".join(c.values()))
+def test_grid_automatic_schedule(grid3m, cfg):
+    """Default (automatic) schedule on a mesh: labels, sampled-edge count,
+    L_max and active set equal the oracle's, hooks are n - c, and the
+    spanning forest is valid and fills exactly the non-minimum slots."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    C, dg, want = grid3m
+    s_lab, e_s = oracle.sample_kout(C.n, C.offsets, C.nbrs, 2)
+    L = oracle.lmax(s_lab, 1024, 1)
+    c = int((want == np.arange(C.n, dtype=np.uint32)).sum())
+    for rep in range(2):
+        say(f"[grid auto] {cfg} rep={rep}")
+        lab, st = G.cc(dg, options=G.Options(sample="kout", **cfg), stats=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(G.to_u32(lab), want), (cfg, rep)
+        assert st["sampled_edges"] == e_s and st["lmax"] == L
+        assert st["active_vertices"] == oracle.active_count(C.n, C.offsets, s_lab, L)
+        if cfg["link"] != "sv":
+            assert st["hooks"] == C.n - c
+    if cfg.get("splice") == "splice_atomic":
+        return
+    fu, fv, lab = G.spanning_forest(dg, options=G.Options(sample="kout", **cfg))
+    torch.cuda.synchronize()
+    fu, fv = G.to_u32(fu), G.to_u32(fv)
+    assert np.array_equal(G.to_u32(lab), want)
+    oracle.check_forest(C.n, C.offsets, C.nbrs, fu, fv, want)
+    assert np.array_equal(fu != G.EMPTY, want != np.arange(C.n, dtype=np.uint32))
