@@ -551,6 +551,7 @@ def batched_bench(G, args) -> dict:
     lb = lab_b.cpu().numpy().view(np.uint32)
     slices = [lb[int(hb.vbase[i]):int(hb.vbase[i]) + g.n] for i, g in enumerate(graphs)]
     same = all(np.array_equal(sl, G.to_u32(l)) for sl, l in zip(slices, labs))
+    batch_block = int(db.c.block)
     del labs, dgs, ws_1, ws_b, db, lab_b
     # the oracle's record of the same batch (per-graph label hashes)
     gold = golden(f"batch{args.batch_graphs}_s{args.seed}")
@@ -572,7 +573,7 @@ def batched_bench(G, args) -> dict:
                         "ER or RMAT by coin flip, edge factor 8..32",
             "graphs": len(graphs), "n": total_n, "m_directed": total_m,
             "classes": {k: tuner.table[k]["choice"] for k in sorted(set(keys))},
-            "batch_block": int(db.c.block),
+            "batch_block": batch_block,
             "batched_ms": round(t_batch * 1e3, 3), "batched_captured_ms": round(t_cap * 1e3, 3),
             "per_graph_launches_ms": round(t_loop * 1e3, 3),
             "speedup": round(t_loop / t_batch, 2),

@@ -33,7 +33,6 @@ CANDIDATES = [
     dict(sample="kout", link="early", find="split"),
     dict(sample="hb", link="rem_cas", find="split", splice="split_one", hb_n=4),
     dict(sample="hb", link="async", find="halve", hb_n=4),
-    dict(sample="kout", link="rem_cas", find="split", splice="splice_atomic"),
 ]
 
 

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+
 #include "gconn_internal.hpp"
 
 namespace gconn {
@@ -58,6 +60,7 @@ __global__ void __launch_bounds__(256) k_random_access(uint32_t* T, uint64_t mas
 }  // namespace gconn
 
 using namespace gconn;
+
 
 extern "C" gconn_status gconn_diag_random_access(uint32_t* table, uint64_t words, int kind,
                                                  uint64_t accesses, uint32_t* sink,

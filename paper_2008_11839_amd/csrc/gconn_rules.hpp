@@ -89,6 +89,29 @@ enum UnionRule : int {
 #define GCONN_ROOT_RECHECK 0
 #endif
 
+// Operation counters of a diagnostic build (GCONN_COUNT_OPS=1): every parent
+// read, CAS and failed CAS of the rules below adds to one of 1024 slots per
+// kind (spread by workgroup so the counting itself does not serialise).
+// Timing of such a build is meaningless; the counts are exact.  Off in
+// every normal build.
+#ifndef GCONN_COUNT_OPS
+#define GCONN_COUNT_OPS 0
+#endif
+#if GCONN_COUNT_OPS
+enum OpKind : int { kOpLoad = 0, kOpLoadAgent = 1, kOpCas = 2, kOpCasFail = 3, kOpStore = 4,
+                    kOpKinds = 8 };
+// one array per translation unit (no relocatable device code)
+static __device__ unsigned long long g_op_count[1024 * kOpKinds];
+__device__ __forceinline__ void count_op(int kind) {
+  atomicAdd(&g_op_count[(blockIdx.x & 1023u) * kOpKinds + kind], 1ull);
+}
+#endif
+#if GCONN_COUNT_OPS && defined(__HIP_DEVICE_COMPILE__)
+#define GCONN_COUNT(kind) count_op(kind)
+#else
+#define GCONN_COUNT(kind) ((void)0)
+#endif
+
 // Read of P inside a find / union loop (see the memory-model note above).  A
 // host build may route it through GCONN_HOST_STALE_LOAD(p), a function that
 // is free to return any value *p held earlier: the CPU test harness uses it
@@ -97,20 +120,26 @@ GCONN_HD uint32_t ld(const uint32_t* p) {
 #if defined(GCONN_HOST_STALE_LOAD) && !defined(__HIP_DEVICE_COMPILE__)
   return GCONN_HOST_STALE_LOAD(p);
 #else
+  GCONN_COUNT(kOpLoad);
   return __hip_atomic_load(p, __ATOMIC_RELAXED, GCONN_P_LOAD_SCOPE);
 #endif
 }
 // Device-coherent read (flags and counters polled across XCDs).
 GCONN_HD uint32_t ld_agent(const uint32_t* p) {
+  GCONN_COUNT(kOpLoadAgent);
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 GCONN_HD void st(uint32_t* p, uint32_t v) {
+  GCONN_COUNT(kOpStore);
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // CAS *p: expected -> desired.  On failure `expected` receives the current value.
 GCONN_HD bool cas(uint32_t* p, uint32_t& expected, uint32_t desired) {
-  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  GCONN_COUNT(kOpCas);
+  const bool ok = __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!ok) GCONN_COUNT(kOpCasFail);
+  return ok;
 }
 GCONN_HD uint32_t amin(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -2859,3 +2859,24 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
 }
 
 }  // namespace gconn
+
+#if GCONN_COUNT_OPS
+// The rules' operation counters of this translation unit (diagnostic builds
+// only; see gconn_rules.hpp): out[kind] summed over the slots.
+extern "C" gconn_status gconn_diag_op_counts(uint64_t* out, int reset) {
+  using namespace gconn;
+  static unsigned long long h[1024 * kOpKinds];
+  GCONN_HIP(hipDeviceSynchronize());
+  GCONN_HIP(hipMemcpyFromSymbol(h, HIP_SYMBOL(g_op_count), sizeof(h)));
+  for (int k = 0; k < kOpKinds; ++k) {
+    unsigned long long t = 0;
+    for (int i = 0; i < 1024; ++i) t += h[i * kOpKinds + k];
+    out[k] = t;
+  }
+  if (reset) {
+    std::memset(h, 0, sizeof(h));
+    GCONN_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_op_count), h, sizeof(h)));
+  }
+  return GCONN_OK;
+}
+#endif
