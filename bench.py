@@ -828,6 +828,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scale", type=int, default=24, help="RMAT scale (24 = the benchmark workload)")
+    ap.add_argument("--workload", default="rmat", choices=("rmat", "grid2d", "grid3d"),
+                    help="main workload (rmat: the benchmark's; the percolation grids 4096^2 "
+                         "at p = 0.7 and 256^3 at p = 0.6 for profiling their kernels)")
+    ap.add_argument("--op-counts", metavar="LIB",
+                    help="load this diagnostic build of the library (python -m "
+                         "paper_2008_11839_amd.build --op-counts LIB) and print the union-find "
+                         "rules' operation counts for one run of the configuration, then exit")
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--sample", default="kout")
@@ -880,6 +887,8 @@ def main() -> int:
 
     import graphgen
     from paper_2008_11839_amd import gconn as G
+    if args.op_counts:
+        G.LIB_PATH = os.path.abspath(args.op_counts)  # before the library is first loaded
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -889,9 +898,19 @@ def main() -> int:
 
     # ------------------------------------------------------------ workload
     t0 = time.time()
-    n = 1 << args.scale
-    src, dst = graphgen.rmat_edges(args.scale, args.edge_factor * n, args.seed)
-    C = graphgen.csr_from_edges(n, src, dst, True, f"rmat{args.scale}_ef{args.edge_factor}_s{args.seed}")
+    if args.workload == "rmat":
+        n = 1 << args.scale
+        src, dst = graphgen.rmat_edges(args.scale, args.edge_factor * n, args.seed)
+        C = graphgen.csr_from_edges(n, src, dst, True,
+                                    f"rmat{args.scale}_ef{args.edge_factor}_s{args.seed}")
+        del src, dst
+    elif args.workload == "grid2d":
+        C = graphgen.grid2d(4096, 4096, 0.7, args.seed)
+        C.name = f"grid2d_4096_p07_s{args.seed}"
+    else:
+        C = graphgen.grid3d(256, 256, 256, 0.6, args.seed)
+        C.name = f"grid3d_256_p06_s{args.seed}"
+    n = C.n
     m = C.m
     log(f"generated {C.name}: n={n} m={m} in {time.time() - t0:.1f}s")
     dg = G.csr(C.offsets, C.nbrs, n)  # uint32 offsets (m < 2^32)
@@ -903,6 +922,24 @@ def main() -> int:
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     ws = G.alloc_workspace(G.workspace_size(dg, opts))
     stream = torch.cuda.current_stream()
+
+    if args.op_counts:
+        import ctypes
+        lib = G.lib()
+        lib.gconn_diag_op_counts.restype = ctypes.c_int
+        lib.gconn_diag_op_counts.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+        cnt = (ctypes.c_uint64 * 8)()
+        G.cc(dg, labels=labels, options=opts, workspace=ws)
+        G._check(lib.gconn_diag_op_counts(cnt, 1))
+        _, st = G.cc(dg, labels=labels, options=opts, workspace=ws, stats=True)
+        G._check(lib.gconn_diag_op_counts(cnt, 1))
+        c = list(cnt)
+        print(json.dumps({"workload": C.name, "options": vars(args), "per_run": {
+            "parent_reads_cached": c[0], "parent_reads_coherent": c[1], "cas": c[2],
+            "cas_failed": c[3], "relaxed_stores": c[4], "compress_chase_loads": c[5],
+            "compress_chase_wave_rounds": c[6], "sampled_entries": st["sampled_edges"],
+            "finish_entries": st["finish_edges"], "hooks": st["hooks"]}}), flush=True)
+        return 0
 
     if args.traffic_workload:
         for _ in range(3):

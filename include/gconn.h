@@ -202,7 +202,8 @@ typedef struct gconn_options {
 /* Counters filled when a stats pointer is passed (the call then synchronises
  * the stream before returning).  Host memory. */
 typedef struct gconn_stats {
-  uint64_t sampled_edges;   /* neighbour entries read by the sampling phase     */
+  uint64_t sampled_edges;   /* neighbour entries read by the sampling phase
+                               (BFS: the row entries of the visited vertices)   */
   uint64_t active_vertices; /* vertices gathered for the finish (label != L_max) */
   uint64_t finish_edges;    /* neighbour entries read by the finish (SV/LT/LP: first round) */
   uint64_t hooks;           /* successful root links (union-find rules)         */

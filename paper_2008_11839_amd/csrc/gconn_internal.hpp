@@ -56,11 +56,6 @@ struct Ctrl {
   uint32_t bfs_convert;               // 1: queue -> bitmap first, 2: bitmap -> queue first
   uint32_t bfs_as_queue;              // the current frontier is held as a queue
   uint32_t bfs_levels;                // levels run
-  // automatic k-out schedule: the locality probe's per-block counts of
-  // sampled edges (local to their id range, all), and the decision
-  uint32_t probe_part[2 * 16];
-  uint32_t probe_done;
-  uint32_t kout_mode;                 // 1: local-first passes, 0: one-pass kernel
 };
 
 struct WsLayout {
@@ -87,6 +82,7 @@ struct WsLayout {
   size_t lrec_src = 0;  // local-first k-out: leaving edges by range and level (uint32)
   size_t lrec_dst = 0;
   size_t lrec_hdr = 0;  //   per range: number of records
+  size_t probe = 0;     // automatic k-out: the locality probe's counts
   uint32_t sub_cap = 0;
   uint64_t seg_cap = 0;
   uint64_t edge_cap = 0;

@@ -99,7 +99,7 @@ enum UnionRule : int {
 #endif
 #if GCONN_COUNT_OPS
 enum OpKind : int { kOpLoad = 0, kOpLoadAgent = 1, kOpCas = 2, kOpCasFail = 3, kOpStore = 4,
-                    kOpKinds = 8 };
+                    kOpChase = 5, kOpChaseRounds = 6, kOpKinds = 8 };
 // one array per translation unit (no relocatable device code)
 static __device__ unsigned long long g_op_count[1024 * kOpKinds];
 __device__ __forceinline__ void count_op(int kind) {
@@ -421,8 +421,11 @@ GCONN_HD bool union_rem_splice(const LinkCtx& c, uint32_t u, uint32_t v, uint32_
       if (cas(&c.P[ru], e, prv)) {
         record_link(c, ru, u, v);
         if constexpr (F != kFindNaive) {
-          find<F>(c.P, u, true);
-          find<F>(c.P, v, true);
+          // P[ru] is now prv, and prv was read as P[rv]: an endpoint that is
+          // ru or rv starts its compressing find from prv (a value its slot
+          // has held) instead of reading it again
+          find<F>(c.P, u, true, (u == ru || u == rv) ? prv : kEmpty);
+          find<F>(c.P, v, true, (v == ru || v == rv) ? prv : kEmpty);
         }
         return true;
       }

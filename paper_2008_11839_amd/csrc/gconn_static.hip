@@ -36,7 +36,71 @@ namespace gconn {
 // --------------------------------------------------------------- setup
 // P[v] = v and empty forest slots, four vertices per lane with 16-byte stores;
 // block 0 also clears the control block.
-__global__ void k_init(Ctrl* c, uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv, int vec) {
+// Locality probe of the automatic k-out schedule, run by blocks 1..16 of
+// k_init (so it costs no launch and no time of its own): 16 x 256 seeded
+// vertices count their sampled edges (first k) and how many stay inside their
+// vertex's id range of the local-first passes, one (inside, all) pair per
+// block in `part`.  The sampling kernels read the pairs and decide the same
+// way each (kout_local_chosen): the local passes when at least a quarter
+// stay inside and the graph spans at least kProbeMinRanges ranges (one
+// workgroup each: fewer cannot fill the chip), otherwise the one-pass kernel.
+// A scrambled RMAT graph keeps about range/n of its sampled edges inside.
+// Exact either way: the choice only picks the schedule.
+constexpr uint32_t kProbeBlocks = 16;
+constexpr uint32_t kProbeMinRanges = 64;
+
+struct KoutProbe {
+  const uint32_t* off32;  // one of the two offset arrays
+  const uint64_t* off64;
+  const uint32_t* nbrs;
+  uint32_t* part;         // 2 * kProbeBlocks counts; null: no probe
+  uint32_t k;
+  uint32_t shift;         // log2 of the local-first range
+  uint64_t seed;
+};
+
+// What the sampling kernels need to read the probe's decision.
+struct KoutGate {
+  const uint32_t* part;  // null: no gate (the kernel always runs)
+  uint32_t n;
+  uint32_t shift;
+};
+
+__device__ __forceinline__ bool kout_local_chosen(const KoutGate& g) {
+  uint64_t loc = 0, tot = 0;
+  for (uint32_t b = 0; b < kProbeBlocks; ++b) {
+    loc += g.part[2 * b];
+    tot += g.part[2 * b + 1];
+  }
+  const uint64_t ranges = ((uint64_t)g.n + (1ull << g.shift) - 1) >> g.shift;
+  return tot > 0 && 4 * loc >= tot && ranges >= kProbeMinRanges;
+}
+
+// Block `b` (1..kProbeBlocks) of k_init: one sample per thread.
+__device__ void kout_probe_block(const KoutProbe& pr, uint32_t n, uint32_t b) {
+  __shared__ uint32_t s_loc, s_tot;
+  if (threadIdx.x == 0) s_loc = s_tot = 0;
+  __syncthreads();
+  const uint64_t j = (uint64_t)(b - 1) * blockDim.x + threadIdx.x;
+  const uint32_t v = (uint32_t)(((splitmix64_at(pr.seed, j) >> 32) * (uint64_t)n) >> 32);
+  const uint64_t o0 = pr.off32 ? pr.off32[v] : pr.off64[v];
+  const uint64_t o1 = pr.off32 ? pr.off32[v + 1] : pr.off64[v + 1];
+  const uint32_t t = (uint32_t)(o1 - o0 < pr.k ? o1 - o0 : pr.k);
+  uint32_t loc = 0;
+  for (uint32_t i = 0; i < t; ++i) loc += (pr.nbrs[o0 + i] >> pr.shift) == (v >> pr.shift);
+  if (t) {
+    atomicAdd(&s_loc, loc);
+    atomicAdd(&s_tot, t);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pr.part[2 * (b - 1)] = s_loc;
+    pr.part[2 * (b - 1) + 1] = s_tot;
+  }
+}
+
+__global__ void k_init(Ctrl* c, uint32_t* P, uint32_t n, uint32_t* fu, uint32_t* fv, int vec,
+                       KoutProbe probe) {
   if (blockIdx.x == 0) {
     uint32_t* w = reinterpret_cast<uint32_t*>(c);
     for (uint32_t i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) w[i] = 0;
@@ -47,6 +111,8 @@ __global__ void k_init(Ctrl* c, uint32_t* P, uint32_t n, uint32_t* fu, uint32_t*
       c->comp_min = kEmpty;
     }
   }
+  if (probe.part && blockIdx.x >= 1 && blockIdx.x <= kProbeBlocks)
+    kout_probe_block(probe, n, blockIdx.x);
   const uint64_t quads = vec ? n / 4 : 0;  // vec: P, fu, fv are 16-byte aligned
   for (uint64_t q = gtid(); q < quads; q += wave_stride()) {
     const uint32_t v = (uint32_t)(4 * q);
@@ -148,8 +214,8 @@ __global__ void k_sample_kout(const OffT* __restrict__ off, const uint32_t* __re
 template <class R, typename OffT>
 __global__ void k_sample_kout_pf(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
                                  uint32_t n, uint32_t k, int random, uint64_t seed, LinkCtx lc,
-                                 Ctrl* stats, const Ctrl* gate) {
-  if (gate && gate->kout_mode != 0) return;  // the automatic schedule chose the local passes
+                                 Ctrl* stats, KoutGate gate) {
+  if (gate.part && kout_local_chosen(gate)) return;  // the automatic schedule chose the local passes
   const uint64_t T = wave_stride();
   uint64_t v = gtid();
   // row of v: start b, degree d, first two sampled neighbours
@@ -355,10 +421,10 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
                                                      uint32_t* P, uint2* res, uint32_t* rsrc,
                                                      uint32_t* rdst, uint32_t* rcnt,
                                                      uint32_t* fu, uint32_t* fv, int local,
-                                                     Ctrl* stats, const Ctrl* gate) {
+                                                     Ctrl* stats, KoutGate gate) {
   extern __shared__ uint32_t L[];  // 2^shift entries
   __shared__ uint32_t nrec;
-  if (gate && gate->kout_mode != 1) return;  // the automatic schedule chose the one-pass kernel
+  if (gate.part && !kout_local_chosen(gate)) return;  // the one-pass kernel was chosen
   const uint32_t range = 1u << shift;
   const uint64_t lo = (uint64_t)blockIdx.x * range;
   const uint32_t len = (uint32_t)min<uint64_t>(range, n - lo);
@@ -461,9 +527,9 @@ __global__ void __launch_bounds__(1024) k_kout_pairs(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ rdst,
                                                      const uint32_t* __restrict__ rcnt,
                                                      uint32_t shift, LinkCtx lc,
-                                                     const Ctrl* gate) {
+                                                     KoutGate gate) {
   extern __shared__ unsigned long long H[];  // kPairSlots keys, ~0 = empty
-  if (gate && gate->kout_mode != 1) return;
+  if (gate.part && !kout_local_chosen(gate)) return;
   for (uint32_t i = threadIdx.x; i < kPairSlots; i += blockDim.x) H[i] = ~0ull;
   __syncthreads();
   const uint32_t cnt = rcnt[blockIdx.x];
@@ -497,62 +563,6 @@ __global__ void __launch_bounds__(1024) k_kout_pairs(const uint32_t* __restrict_
       }
     }
     if (fresh) R::unite_pair(lc, a, b, v, w);
-  }
-}
-
-// Locality probe of the automatic k-out schedule: kProbeBlocks x 256 seeded
-// vertices count their sampled edges and how many stay inside the vertex's
-// own local-first id range; the last block to finish decides.  The local
-// passes run when at least a quarter of the sampled edges are range-local --
-// meshes and other graphs whose ids follow their geometry -- and the
-// one-pass kernel runs otherwise (a scrambled RMAT graph keeps ~range/n of
-// them), provided the graph spans at least kProbeMinRanges ranges (one
-// workgroup each: fewer cannot fill the chip).  Exact either way: the choice
-// only picks the schedule.
-constexpr uint32_t kProbeBlocks = 16;
-constexpr uint32_t kProbeMinRanges = 64;
-
-template <typename OffT>
-__global__ void __launch_bounds__(256) k_kout_probe(const OffT* __restrict__ off,
-                                                    const uint32_t* __restrict__ nbrs, uint32_t n,
-                                                    uint32_t k, uint32_t shift, uint64_t seed,
-                                                    Ctrl* c) {
-  __shared__ uint32_t s_loc, s_tot, s_last;
-  if (threadIdx.x == 0) s_loc = s_tot = 0;
-  __syncthreads();
-  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t v = (uint32_t)(((splitmix64_at(seed, j) >> 32) * (uint64_t)n) >> 32);
-  uint32_t loc = 0, tot = 0;
-  if (v < n) {
-    const uint64_t b = off[v], d = (uint64_t)off[v + 1] - b;
-    const uint32_t t = (uint32_t)(d < k ? d : k);
-    for (uint32_t i = 0; i < t; ++i) {
-      ++tot;
-      loc += (nbrs[b + i] >> shift) == (v >> shift);
-    }
-  }
-  if (tot) {
-    atomicAdd(&s_loc, loc);
-    atomicAdd(&s_tot, tot);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    c->probe_part[2 * blockIdx.x] = s_loc;
-    c->probe_part[2 * blockIdx.x + 1] = s_tot;
-    __threadfence();
-    s_last = atomicAdd(&c->probe_done, 1u) == kProbeBlocks - 1;
-  }
-  __syncthreads();
-  if (s_last && threadIdx.x == 0) {
-    __threadfence();
-    uint64_t L = 0, T = 0;
-    for (uint32_t b = 0; b < kProbeBlocks; ++b) {
-      L += __hip_atomic_load(&c->probe_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      T += __hip_atomic_load(&c->probe_part[2 * b + 1], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const uint64_t ranges = ((uint64_t)n + (1ull << shift) - 1) >> shift;
-    c->kout_mode = (T > 0 && 4 * L >= T && ranges >= kProbeMinRanges) ? 1u : 0u;
   }
 }
 
@@ -1177,8 +1187,12 @@ __global__ void k_compress_gather(const OffT* __restrict__ off, uint32_t* P, uin
       while (more) {  // lockstep pointer jumping of the four chases
         more = false;
         uint32_t q[4];
+        if (lane() == 0) GCONN_COUNT(kOpChaseRounds);  // diagnostic builds: one per wave round
 #pragma unroll
-        for (int k = 0; k < 4; ++k) q[k] = (r[k] != v0 + k && v0 + k < n) ? P[r[k]] : r[k];
+        for (int k = 0; k < 4; ++k) {
+          if (r[k] != v0 + k && v0 + k < n) GCONN_COUNT(kOpChase);
+          q[k] = (r[k] != v0 + k && v0 + k < n) ? P[r[k]] : r[k];
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if (q[k] != r[k]) {
@@ -1557,9 +1571,17 @@ __global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) 
     }
     best = key > best ? key : best;
   }
-  // every lane of a wave ran the same iterations, so all are active here
+  // every lane of a wave ran the same iterations, so all are active here;
+  // then the workgroup's waves combine in LDS: one atomic per workgroup (the
+  // key is a single address, where device atomics serialise at ~11 ns each)
+  __shared__ unsigned long long wmax[16];
   best = wave_max(best);
-  if (lane() == 0 && best) atomicMax(&c->bfs_key, best);
+  if (lane() == 0) wmax[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < (blockDim.x + 63) / 64; ++w) best = wmax[w] > best ? wmax[w] : best;
+    if (best) atomicMax(&c->bfs_key, best);
+  }
 }
 
 template <typename OffT>
@@ -1843,10 +1865,27 @@ __global__ void k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restric
 // Re-root the BFS component at its minimum id (the BFS labels reached vertices
 // with the source, which is not the component minimum).
 __global__ void k_bfs_min(const uint32_t* __restrict__ visited, uint32_t words, Ctrl* c) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
-       i += wave_stride()) {
-    uint32_t w = visited[i];
-    if (w) atomicMin(&c->comp_min, (uint32_t)(i * 32 + (__ffs(w) - 1)));
+  // the first visited id of the lane's words, then of the wave and the
+  // workgroup: one atomic per workgroup on the single-address minimum
+  uint32_t best = kEmpty;
+  for (uint64_t base = wave_base(); base < words; base += wave_stride()) {
+    const uint64_t i = base + lane();
+    const uint32_t w = i < words ? visited[i] : 0u;
+    if (w) {
+      const uint32_t id = (uint32_t)(i * 32 + (__ffs(w) - 1));
+      best = id < best ? id : best;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t o = __shfl_xor(best, d);
+    best = o < best ? o : best;
+  }
+  __shared__ uint32_t wmin[16];
+  if (lane() == 0) wmin[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < (blockDim.x + 63) / 64; ++w) best = wmin[w] < best ? wmin[w] : best;
+    if (best != kEmpty) atomicMin(&c->comp_min, best);
   }
 }
 
@@ -2022,6 +2061,7 @@ struct Run {
   Ctrl* ctrl;
   WorkLists wl;
   uint32_t* hooks;
+  uint32_t* probe_part = nullptr;  // set when k_init ran the automatic schedule's probe
   uint64_t rounds = 0;
 
   Run(const gconn_graph& g_, uint32_t* P_, uint32_t* fu_, uint32_t* fv_, uint8_t* ws_,
@@ -2145,7 +2185,7 @@ struct Run {
   // the plain two-pass schedule.  gate (nullable): the automatic schedule's
   // control block; the local passes then run only if its probe chose them.
   template <typename OffT>
-  gconn_status local_passes(bool local, const Ctrl* gate) {
+  gconn_status local_passes(bool local, KoutGate gate) {
     const OffT* off = static_cast<const OffT*>(g.offsets);
     const uint32_t n = g.n;
     Ctrl* st = want_stats ? ctrl : nullptr;
@@ -2186,7 +2226,7 @@ struct Run {
     GCONN_TRY(prof_mark(kPhaseSample, true, s));
     if (o.sample == GCONN_SAMPLE_KOUT) {
       if (kout_local_applies(o)) {
-        GCONN_TRY(local_passes<OffT>(o.kout_local != 0, nullptr));
+        GCONN_TRY(local_passes<OffT>(o.kout_local != 0, KoutGate{}));
       } else if (kout_xcd_applies(o)) {
         uint32_t* rsrc = reinterpret_cast<uint32_t*>(ws + L.kx_src);
         uint32_t* rdst = reinterpret_cast<uint32_t*>(ws + L.kx_dst);
@@ -2265,15 +2305,12 @@ struct Run {
       } else {
         // Automatic schedule: the locality probe picks the local-first passes
         // or the one-pass kernel on the device; the other side returns at once.
-        const Ctrl* gate = nullptr;
-        if (kout_auto_local_applies(o)) {
+        KoutGate gate{};
+        if (probe_part) {  // k_init probed the graph
           uint32_t range = kLocalRangeMin, shift = 0;
           GCONN_TRY(local_range<OffT>(&range));
           while ((1u << shift) < range) ++shift;
-          k_kout_probe<OffT><<<kProbeBlocks, 256, 0, s>>>(off, g.nbrs, n, o.k, shift,
-                                                          o.seed ^ 0x70726f6265ull, ctrl);
-          GCONN_LAUNCHED("k_kout_probe");
-          gate = ctrl;
+          gate = KoutGate{probe_part, n, shift};
           GCONN_TRY(local_passes<OffT>(true, gate));
         }
         GCONN_TRY(with_rule(o.link, o.find, o.splice, [&](auto rule) -> gconn_status {
@@ -2318,7 +2355,7 @@ struct Run {
                           reinterpret_cast<uint32_t*>(ws + L.queue1)};
     k_fill<<<gridN(words), block, 0, s>>>(visited, 0u, words);
     GCONN_LAUNCHED("k_fill(visited)");
-    k_bfs_argmax<OffT><<<gridN(n), block, 0, s>>>(off, n, ctrl);
+    k_bfs_argmax<OffT><<<std::min<uint32_t>(gridN(n), 1024), block, 0, s>>>(off, n, ctrl);
     GCONN_LAUNCHED("k_bfs_argmax");
     k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0]);
     GCONN_LAUNCHED("k_bfs_start");
@@ -2369,7 +2406,7 @@ struct Run {
       GCONN_HIP(hipStreamSynchronize(s));
       rounds = levels;
     }
-    k_bfs_min<<<gridN(words), block, 0, s>>>(visited, words, ctrl);
+    k_bfs_min<<<std::min<uint32_t>(gridN(words), 1024), block, 0, s>>>(visited, words, ctrl);
     GCONN_LAUNCHED("k_bfs_min");
     k_bfs_label<<<gridN(n), block, 0, s>>>(visited, n, ctrl, P);
     GCONN_LAUNCHED("k_bfs_label");
@@ -2494,7 +2531,7 @@ struct Run {
 gconn_status reset_ctrl_and_parents(Ctrl* ctrl, uint32_t* P, uint32_t n, hipStream_t s) {
   const bool vec = (reinterpret_cast<uintptr_t>(P) % 16) == 0;
   k_init<<<grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), 256), 256, 0, s>>>(
-      ctrl, P, n, nullptr, nullptr, vec ? 1 : 0);
+      ctrl, P, n, nullptr, nullptr, vec ? 1 : 0, KoutProbe{});
   GCONN_LAUNCHED("k_init");
   return GCONN_OK;
 }
@@ -2715,6 +2752,7 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
   if (needs_claims(o.link)) L.hooks = take(4 * n);
   if (csr && (kout_prelink_applies(o) || (kout_local_applies(o) && !o.kout_local)))
     L.resid = take(8 * n);
+  if (csr && kout_auto_local_applies(o)) L.probe = take(8 * kProbeBlocks);
   if (csr && ((kout_local_applies(o) && o.kout_local) || kout_auto_local_applies(o))) {
     // records: at most two per vertex, in per-range blocks of 2 * range
     const uint64_t cap = 2 * (n + kLocalRangeMax);
@@ -2787,8 +2825,26 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
     k_ctrl_init<<<1, 256, 0, s>>>(run.ctrl);
     GCONN_LAUNCHED("k_ctrl_init");
   } else {
-    k_init<<<grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), block), block, 0, s>>>(
-        run.ctrl, P, n, fu, fv, vec ? 1 : 0);
+    // the automatic k-out schedule's locality probe rides in block 0
+    KoutProbe probe{};
+    const uint32_t init_grid = grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), block);
+    if (g.format == GCONN_CSR && n > 0 && g.m > 0 && kout_auto_local_applies(o) &&
+        init_grid > kProbeBlocks) {
+      uint32_t range = kLocalRangeMin;
+      GCONN_TRY(g.offsets_64 ? Run::local_range<uint64_t>(&range)
+                             : Run::local_range<uint32_t>(&range));
+      uint32_t shift = 0;
+      while ((1u << shift) < range) ++shift;
+      probe.off32 = g.offsets_64 ? nullptr : static_cast<const uint32_t*>(g.offsets);
+      probe.off64 = g.offsets_64 ? static_cast<const uint64_t*>(g.offsets) : nullptr;
+      probe.nbrs = g.nbrs;
+      probe.part = reinterpret_cast<uint32_t*>(ws + L.probe);
+      probe.k = o.k;
+      probe.shift = shift;
+      probe.seed = o.seed ^ 0x70726f6265ull;
+      run.probe_part = probe.part;
+    }
+    k_init<<<init_grid, block, 0, s>>>(run.ctrl, P, n, fu, fv, vec ? 1 : 0, probe);
     GCONN_LAUNCHED("k_init");
   }
   if (run.hooks) GCONN_TRY(launch_fill(run.hooks, kEmpty, n, s));
@@ -2847,7 +2903,9 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
   if (stats) {
     Ctrl h;
     GCONN_TRY(run.read_ctrl(&h));
-    stats->sampled_edges = h.stat_sampled;
+    // BFS sampling reads whole rows: the entries of the visited vertices
+    stats->sampled_edges =
+        (sampled && o.sample == GCONN_SAMPLE_BFS) ? h.explored_edges : h.stat_sampled;
     stats->active_vertices = h.stat_active;
     stats->finish_edges = h.stat_finish_edges;
     stats->hooks = h.stat_hooks;
