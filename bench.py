@@ -842,7 +842,7 @@ def main() -> int:
     ap.add_argument("--find", default="split")
     ap.add_argument("--splice", default="splice_atomic",
                     help="Union-Rem-CAS splice rule (the spanning-forest leg uses split_one "
-                         "when this is splice_atomic, which links non-roots)")
+                         "with FindNaive when this is splice_atomic, which links non-roots)")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--kout-prelink", type=int, default=0, choices=(0, 1))
     ap.add_argument("--kout-local", type=int, default=0, choices=(0, 1))
@@ -1099,9 +1099,15 @@ def main() -> int:
     if not args.no_extras:
         fu = torch.empty(n, dtype=torch.int32, device=dev)
         fv = torch.empty(n, dtype=torch.int32, device=dev)
-        # a forest needs root-based links: Rem's SpliceAtomic re-hangs non-roots
-        sf_splice = "split_one" if args.splice == "splice_atomic" else args.splice
-        sf_opts = G.Options(sample=args.sample, link=args.link, find=args.find, splice=sf_splice,
+        # a forest needs root-based links: Rem's SpliceAtomic re-hangs non-roots.
+        # In its place SplitAtomicOne with no compressing finds during the
+        # unions (the full compress pass after sampling flattens the trees),
+        # the fastest root-based pair on RMAT-24: finds after each link cost
+        # more than the shorter paths they leave save
+        sf_splice, sf_find = args.splice, args.find
+        if args.splice == "splice_atomic":
+            sf_splice, sf_find = "split_one", "naive"
+        sf_opts = G.Options(sample=args.sample, link=args.link, find=sf_find, splice=sf_splice,
                             block=args.block, kout_prelink=bool(args.kout_prelink),
                             kout_local=bool(args.kout_local), schedule=args.schedule,
                             atomic_compress=bool(args.atomic_compress))
@@ -1125,7 +1131,10 @@ def main() -> int:
         filled = int((fu != -1).sum().item())
         comps = int((torch.from_numpy(got.view(np.int32)).to(dev) ==
                      torch.arange(n, dtype=torch.int32, device=dev)).sum().item())
-        result["spanning_forest"] = {"splice": sf_splice, "ms_per_step": round(sf_ms, 5),
+        result["spanning_forest"] = {"splice": sf_splice, "find": sf_find,
+                                     "ms_per_step": round(sf_ms, 5),
+                                     "cc_ms_per_step": round(ms_per_step, 5),
+                                     "vs_cc": round(sf_ms / ms_per_step, 3),
                                      "gedges_per_s": round(m / (sf_ms * 1e-3) / 1e9, 2),
                                      "forest_edges": filled, "n_minus_c": n - comps}
         log(f"spanning forest {sf_ms:.4f} ms/step, {filled} edges (n-c = {n - comps})")

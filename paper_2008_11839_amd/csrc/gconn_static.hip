@@ -1826,36 +1826,170 @@ __global__ void k_bits_to_queue(const uint32_t* __restrict__ bits, uint32_t word
   }
 }
 
-// Bottom-up: every unvisited vertex looks for a neighbour in the frontier.
+// Bottom-up level: every unvisited vertex looks for a neighbour in the
+// frontier, and the first one in its row becomes its parent (the choice a
+// sequential scan of the row makes).  A lane takes four consecutive vertices,
+// so eight lanes share one visited word and write it once, with no atomic:
+// only this level's lanes for those vertices change it.  The first kBuHead
+// entries of the four rows are tried with their loads in flight together;
+// what remains of the rows is then spread over the wave, 64 entries a step,
+// so that one long row does not keep 63 lanes waiting, and a row whose parent
+// is known is skipped from the next step on.  Entries of one row found in the
+// same step are resolved by an LDS minimum over their positions.
+constexpr uint32_t kBuHead = 2;
+constexpr uint32_t kBuBlock = 256;
+constexpr uint32_t kBuSlots = 256;  // vertices of one wave iteration
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <typename OffT>
-__global__ void k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
-                         uint32_t n, uint32_t* visited, const uint32_t* __restrict__ fr_in,
-                         uint32_t* fr_out, Ctrl* c, uint32_t nxt, uint32_t* fu, uint32_t* fv) {
+__global__ void __launch_bounds__(kBuBlock)
+k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs, uint32_t n,
+         uint32_t* visited, const uint32_t* __restrict__ fr_in, uint32_t* fr_out, Ctrl* c,
+         uint32_t nxt, uint32_t* fu, uint32_t* fv) {
   if (c->bfs_mode != 2) return;
+  // per wave: first flattened position of each slot's remaining entries,
+  // where they start in nbrs, and the best (position << 32 | neighbour) found
+  __shared__ uint64_t s_ex[kBuBlock / 64][kBuSlots + 1];
+  __shared__ uint64_t s_start[kBuBlock / 64][kBuSlots];
+  __shared__ unsigned long long s_best[kBuBlock / 64][kBuSlots];
+  const uint32_t wv = threadIdx.x >> 6, ln = lane();
+  constexpr unsigned long long kNone = ~0ull;
   unsigned long long found = 0, found_edges = 0;
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    const uint64_t v = base + lane();
-    if (v < n && !(visited[v >> 5] & (1u << (v & 31)))) {
-      const uint64_t b = off[v], e = off[v + 1];
-      for (uint64_t x = b; x < e; ++x) {
-        const uint32_t w = nbrs[x];
-        if (fr_in[w >> 5] & (1u << (w & 31))) {
-          atomicOr(&visited[v >> 5], 1u << (v & 31));
-          atomicOr(&fr_out[v >> 5], 1u << (v & 31));
-          if (fu) {
-            fu[v] = w;
-            fv[v] = (uint32_t)v;
+  const uint64_t quads = ((uint64_t)n + 3) / 4;
+  for (uint64_t base = wave_base(); base < quads; base += wave_stride()) {
+    const uint64_t q = base + ln;
+    const uint64_t v0 = q * 4;
+    const uint32_t sh = (uint32_t)(v0 & 31);
+    const uint32_t vis = q < quads ? visited[v0 >> 5] : 0xFFFFFFFFu;
+    uint64_t cur[4], end[4];
+    uint32_t deg[4], par[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cur[j] = end[j] = 0;
+      par[j] = kEmpty;
+      if (q < quads && v0 + j < n && !((vis >> (sh + j)) & 1u)) {
+        cur[j] = off[v0 + j];
+        end[j] = off[v0 + j + 1];
+      }
+      deg[j] = (uint32_t)(end[j] - cur[j]);
+    }
+#pragma unroll
+    for (uint32_t h = 0; h < kBuHead; ++h) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = cur[j] < end[j] ? nbrs[cur[j]] : 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (cur[j] < end[j]) {
+          if ((fr_in[w[j] >> 5] >> (w[j] & 31)) & 1u) {
+            par[j] = w[j];
+            end[j] = cur[j];
+          } else {
+            ++cur[j];
           }
-          ++found;
-          found_edges += e - b;
-          break;
         }
       }
+    }
+    uint64_t rem[4], lane_rem = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rem[j] = end[j] - cur[j];
+      lane_rem += rem[j];
+    }
+    // exclusive prefix of the remaining entries over the wave (64-bit: one
+    // row may hold more than 2^32 / 256 entries)
+    uint64_t incl = lane_rem;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(incl, d);
+      if (ln >= (uint32_t)d) incl += y;
+    }
+    const uint64_t total = __shfl(incl, 63);
+    if (total) {
+      uint64_t ex = incl - lane_rem;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s_ex[wv][ln * 4 + j] = ex;
+        s_start[wv][ln * 4 + j] = cur[j];
+        s_best[wv][ln * 4 + j] = kNone;
+        ex += rem[j];
+      }
+      if (ln == 63) s_ex[wv][kBuSlots] = total;
+      wave_lds_sync();
+      uint64_t i0 = 0;
+      for (;;) {
+        const uint64_t i = i0 + ln;
+        if (i < total) {
+          // the slot whose remaining entries hold position i: the last slot
+          // starting at or before i (empty slots start where the next does)
+          uint32_t sl = 0;
+          for (uint32_t step = kBuSlots / 2; step; step >>= 1)
+            if (s_ex[wv][sl + step] <= i) sl += step;
+          if (s_best[wv][sl] == kNone) {
+            const uint64_t k = i - s_ex[wv][sl];
+            const uint32_t w = nbrs[s_start[wv][sl] + k];
+            if ((fr_in[w >> 5] >> (w & 31)) & 1u)
+              atomicMin(&s_best[wv][sl], (k << 32) | w);
+          }
+        }
+        wave_lds_sync();
+        i0 += 64;
+        if (i0 >= total) break;
+        // continue at the first position >= i0 of a slot still without parent
+        unsigned long long nx = kNone;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t sl = ln * 4 + j;
+          const uint64_t a = s_ex[wv][sl], e = a + rem[j];
+          if (rem[j] && e > i0 && s_best[wv][sl] == kNone) {
+            const uint64_t at = a > i0 ? a : i0;
+            nx = at < nx ? at : nx;
+          }
+        }
+        for (int d = 32; d >= 1; d >>= 1) {
+          const unsigned long long y = __shfl_xor(nx, d);
+          nx = y < nx ? y : nx;
+        }
+        if (nx == kNone) break;
+        i0 = nx;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned long long b = s_best[wv][ln * 4 + j];
+        if (rem[j] && b != kNone) par[j] = (uint32_t)b;
+      }
+      wave_lds_sync();  // the next iteration rewrites the slots
+    }
+    uint32_t mask = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (par[j] != kEmpty) {
+        mask |= 1u << (sh + j);
+        ++found;
+        found_edges += deg[j];
+        if (fu) {
+          fu[v0 + j] = par[j];
+          fv[v0 + j] = (uint32_t)(v0 + j);
+        }
+      }
+    }
+    // the eight lanes of one visited word combine their bits; the first
+    // writes the word (it is the only writer of those 32 vertices' bits)
+    mask |= __shfl_xor(mask, 1);
+    mask |= __shfl_xor(mask, 2);
+    mask |= __shfl_xor(mask, 4);
+    if ((ln & 7) == 0 && mask) {
+      visited[v0 >> 5] = vis | mask;
+      fr_out[v0 >> 5] = mask;
     }
   }
   found = wave_sum(found);
   found_edges = wave_sum(found_edges);
-  if (lane() == 0 && found) {
+  if (ln == 0 && found) {
     atomicAdd(&c->frontier_count[nxt], (uint32_t)found);
     atomicAdd(&c->frontier_edges[nxt], found_edges);
     atomicAdd(&c->explored_edges, found_edges);
@@ -2367,6 +2501,8 @@ struct Run {
     const uint32_t td_grid = persistent_grid(k_bfs_td<OffT>, 256);
     const uint32_t fixed = std::min<uint32_t>(gridN(n), kPersistentBlocks);
     const uint32_t wgrid = std::min<uint32_t>(gridN(words), kPersistentBlocks);
+    const uint32_t bu_grid = (uint32_t)std::min<uint64_t>(
+        ((uint64_t)n / 4 + kBuBlock) / kBuBlock, kPersistentBlocks);
     for (uint64_t level = 0;; level += kRoundsPerSync) {
       for (int j = 0; j < kRoundsPerSync; ++j) {
         const uint32_t cur = (uint32_t)((level + j) & 1), nxt = cur ^ 1;
@@ -2379,8 +2515,8 @@ struct Run {
         GCONN_LAUNCHED("k_queue_to_bits");
         k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[nxt], words, ctrl, 0);
         GCONN_LAUNCHED("k_bfs_clear_bits");
-        k_bfs_bu<OffT><<<fixed, block, 0, s>>>(off, g.nbrs, n, visited, bits[cur], bits[nxt],
-                                               ctrl, nxt, fu, fv);
+        k_bfs_bu<OffT><<<bu_grid, kBuBlock, 0, s>>>(off, g.nbrs, n, visited, bits[cur],
+                                                    bits[nxt], ctrl, nxt, fu, fv);
         GCONN_LAUNCHED("k_bfs_bu");
         // top-down: the frontier as a queue (from the bits if it was those)
         k_bits_to_queue<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
