@@ -71,6 +71,7 @@ struct WsLayout {
   size_t visited = 0; // BFS bitmap
   size_t fr_bits0 = 0, fr_bits1 = 0;  // BFS frontier bitmaps
   size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
+  size_t bfs_stripes = 0;             // BFS per-level counter stripes
   size_t resid = 0;   // k-out pre-link: residual sampled edges (uint2[n])
   size_t words = 0;   // Union-JTB (rank, parent) words (uint64[n])
   size_t roots = 0;   // Union-JTB flat roots after sampling (uint32[n])

@@ -1584,9 +1584,44 @@ __global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) 
   }
 }
 
+// A level's discovered vertices and their row entries are added up by the
+// level's workgroups into 64 stripes (one 128-byte line each, workgroup i into
+// stripe i mod 64) instead of into one counter: device atomics on a single
+// address serialise at about 11 ns each, which for thousands of workgroups is
+// most of a level.  The next level's decision kernel folds the stripes of its
+// frontier into the counters and clears them.
+struct alignas(128) BfsStripe {
+  unsigned long long count, edges;
+};
+constexpr uint32_t kBfsStripes = 64;
+
+__device__ __forceinline__ void bfs_stripe_add(BfsStripe* st, uint32_t level_slot,
+                                               unsigned long long count,
+                                               unsigned long long edges) {
+  // whole workgroup: wave sums, then one atomic pair from thread 0
+  __shared__ unsigned long long part[2][16];
+  count = wave_sum(count);
+  edges = wave_sum(edges);
+  if (lane() == 0) {
+    part[0][threadIdx.x >> 6] = count;
+    part[1][threadIdx.x >> 6] = edges;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (uint32_t w = 1; w < (blockDim.x + 63) / 64; ++w) {
+      count += part[0][w];
+      edges += part[1][w];
+    }
+    BfsStripe* t = st + level_slot * kBfsStripes + (blockIdx.x % kBfsStripes);
+    if (count) atomicAdd(&t->count, count);
+    if (edges) atomicAdd(&t->edges, edges);
+  }
+}
+
 template <typename OffT>
 __global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* visited,
-                            uint32_t* queue0) {
+                            uint32_t* queue0, BfsStripe* st) {
+  for (uint32_t i = threadIdx.x; i < 2 * kBfsStripes; i += blockDim.x) st[i].count = st[i].edges = 0;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     uint32_t s = (uint32_t)(0xFFFFFFFFull - (c->bfs_key & 0xFFFFFFFFull));
     c->bfs_source = s;
@@ -1613,8 +1648,21 @@ __global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* vis
 // integers -- note which representation change the level needs first, and
 // clear the counters of frontier `nxt`.  Every later kernel of the level
 // reads bfs_mode and returns at once when the level is not its kind.
-__global__ void k_bfs_decide(Ctrl* c, uint32_t cur, uint64_t m, uint32_t n) {
+__global__ void k_bfs_decide(Ctrl* c, BfsStripe* st, uint32_t cur, uint64_t m, uint32_t n) {
   __shared__ uint32_t run;
+  if (threadIdx.x < 64) {
+    // fold the stripes of frontier `cur` into its counters (wave 0)
+    BfsStripe* t = st + cur * kBfsStripes + threadIdx.x;
+    unsigned long long sc = t->count, se = t->edges;
+    t->count = t->edges = 0;
+    sc = wave_sum(sc);
+    se = wave_sum(se);
+    if (threadIdx.x == 0 && (sc || se)) {
+      c->frontier_count[cur] += (uint32_t)sc;
+      c->frontier_edges[cur] += se;
+      c->explored_edges += se;
+    }
+  }
   if (threadIdx.x == 0) {
     const uint32_t count = c->frontier_count[cur];
     run = c->bfs_mode != 0 && count != 0;
@@ -1706,8 +1754,9 @@ __device__ __forceinline__ bool bfs_claim(bool valid, uint32_t w, uint32_t* visi
 template <typename OffT>
 __global__ void __launch_bounds__(256) k_bfs_td(const OffT* __restrict__ off,
                                                 const uint32_t* __restrict__ nbrs, WorkLists wl,
-                                                Ctrl* c, uint32_t nxt, uint32_t* visited,
-                                                uint32_t* queue_out, uint32_t* fu, uint32_t* fv) {
+                                                Ctrl* c, BfsStripe* st, uint32_t nxt,
+                                                uint32_t* visited, uint32_t* queue_out,
+                                                uint32_t* fu, uint32_t* fv) {
   __shared__ uint32_t pre_s[kSubLists + 1], pre_m[kSubLists + 1];
   __shared__ uint32_t stage[kBfsStage];
   __shared__ uint32_t staged, base_out;
@@ -1793,11 +1842,8 @@ __global__ void __launch_bounds__(256) k_bfs_td(const OffT* __restrict__ off,
   if (threadIdx.x == 0 && kept) base_out = atomicAdd(&c->frontier_count[nxt], kept);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < kept; i += blockDim.x) queue_out[base_out + i] = stage[i];
-  edges = wave_sum(edges);
-  if (lane() == 0 && edges) {
-    atomicAdd(&c->frontier_edges[nxt], edges);
-    atomicAdd(&c->explored_edges, edges);
-  }
+  // the vertex count is the queue cursor itself; the row entries go to a stripe
+  bfs_stripe_add(st, nxt, 0, edges);
 }
 
 __global__ void k_queue_to_bits(const uint32_t* __restrict__ queue, const Ctrl* c, uint32_t cur,
@@ -1836,7 +1882,10 @@ __global__ void k_bits_to_queue(const uint32_t* __restrict__ bits, uint32_t word
 // so that one long row does not keep 63 lanes waiting, and a row whose parent
 // is known is skipped from the next step on.  Entries of one row found in the
 // same step are resolved by an LDS minimum over their positions.
-constexpr uint32_t kBuHead = 2;
+#ifndef GCONN_BU_HEAD
+#define GCONN_BU_HEAD 2
+#endif
+constexpr uint32_t kBuHead = GCONN_BU_HEAD;
 constexpr uint32_t kBuBlock = 256;
 constexpr uint32_t kBuSlots = 256;  // vertices of one wave iteration
 
@@ -1850,7 +1899,7 @@ template <typename OffT>
 __global__ void __launch_bounds__(kBuBlock)
 k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs, uint32_t n,
          uint32_t* visited, const uint32_t* __restrict__ fr_in, uint32_t* fr_out, Ctrl* c,
-         uint32_t nxt, uint32_t* fu, uint32_t* fv) {
+         BfsStripe* st, uint32_t nxt, uint32_t* fu, uint32_t* fv) {
   if (c->bfs_mode != 2) return;
   // per wave: first flattened position of each slot's remaining entries,
   // where they start in nbrs, and the best (position << 32 | neighbour) found
@@ -1865,40 +1914,53 @@ k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs, uint32
     const uint64_t q = base + ln;
     const uint64_t v0 = q * 4;
     const uint32_t sh = (uint32_t)(v0 & 31);
-    const uint32_t vis = q < quads ? visited[v0 >> 5] : 0xFFFFFFFFu;
-    uint64_t cur[4], end[4];
+    // the visited word and the five row bounds are loaded together (a
+    // visited vertex's row is then ignored), and so are the first kBuHead
+    // entries of the four rows and their frontier words: three dependent
+    // loads in all
+    const bool live = q < quads;
+    const uint32_t vis = live ? visited[v0 >> 5] : 0xFFFFFFFFu;
+    OffT ob[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) ob[j] = live ? off[v0 + j < n ? v0 + j : n] : (OffT)0;
+    OffT cur[4], end[4];
     uint32_t deg[4], par[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      cur[j] = end[j] = 0;
-      par[j] = kEmpty;
-      if (q < quads && v0 + j < n && !((vis >> (sh + j)) & 1u)) {
-        cur[j] = off[v0 + j];
-        end[j] = off[v0 + j + 1];
-      }
+      const bool todo = live && v0 + j < n && !((vis >> (sh + j)) & 1u);
+      cur[j] = ob[j];
+      end[j] = todo ? ob[j + 1] : ob[j];
       deg[j] = (uint32_t)(end[j] - cur[j]);
+      par[j] = kEmpty;
     }
+    {
+      uint32_t w[4][kBuHead], f[4][kBuHead];
 #pragma unroll
-    for (uint32_t h = 0; h < kBuHead; ++h) {
-      uint32_t w[4];
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) w[j] = cur[j] < end[j] ? nbrs[cur[j]] : 0u;
+        for (uint32_t h = 0; h < kBuHead; ++h) w[j][h] = h < end[j] - cur[j] ? nbrs[cur[j] + h] : 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (uint32_t h = 0; h < kBuHead; ++h)
+          f[j][h] = h < end[j] - cur[j] ? fr_in[w[j][h] >> 5] >> (w[j][h] & 31) : 0u;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (cur[j] < end[j]) {
-          if ((fr_in[w[j] >> 5] >> (w[j] & 31)) & 1u) {
-            par[j] = w[j];
-            end[j] = cur[j];
-          } else {
-            ++cur[j];
+        bool hit = false;
+#pragma unroll
+        for (uint32_t h = 0; h < kBuHead; ++h) {
+          if (!hit && (f[j][h] & 1u)) {
+            par[j] = w[j][h];
+            hit = true;
           }
         }
+        cur[j] = (hit || end[j] - cur[j] <= kBuHead) ? end[j] : cur[j] + kBuHead;
       }
     }
     uint64_t rem[4], lane_rem = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      rem[j] = end[j] - cur[j];
+      rem[j] = (uint64_t)(end[j] - cur[j]);
       lane_rem += rem[j];
     }
     // exclusive prefix of the remaining entries over the wave (64-bit: one
@@ -1914,7 +1976,7 @@ k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs, uint32
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         s_ex[wv][ln * 4 + j] = ex;
-        s_start[wv][ln * 4 + j] = cur[j];
+        s_start[wv][ln * 4 + j] = (uint64_t)cur[j];
         s_best[wv][ln * 4 + j] = kNone;
         ex += rem[j];
       }
@@ -1987,13 +2049,7 @@ k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs, uint32
       fr_out[v0 >> 5] = mask;
     }
   }
-  found = wave_sum(found);
-  found_edges = wave_sum(found_edges);
-  if (ln == 0 && found) {
-    atomicAdd(&c->frontier_count[nxt], (uint32_t)found);
-    atomicAdd(&c->frontier_edges[nxt], found_edges);
-    atomicAdd(&c->explored_edges, found_edges);
-  }
+  bfs_stripe_add(st, nxt, found, found_edges);
 }
 
 // Re-root the BFS component at its minimum id (the BFS labels reached vertices
@@ -2491,7 +2547,8 @@ struct Run {
     GCONN_LAUNCHED("k_fill(visited)");
     k_bfs_argmax<OffT><<<std::min<uint32_t>(gridN(n), 1024), block, 0, s>>>(off, n, ctrl);
     GCONN_LAUNCHED("k_bfs_argmax");
-    k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0]);
+    BfsStripe* stripes = reinterpret_cast<BfsStripe*>(ws + L.bfs_stripes);
+    k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0], stripes);
     GCONN_LAUNCHED("k_bfs_start");
     // Levels run kRoundsPerSync at a time between host checks: each level's
     // direction and representation changes are decided on the device
@@ -2506,7 +2563,7 @@ struct Run {
     for (uint64_t level = 0;; level += kRoundsPerSync) {
       for (int j = 0; j < kRoundsPerSync; ++j) {
         const uint32_t cur = (uint32_t)((level + j) & 1), nxt = cur ^ 1;
-        k_bfs_decide<<<1, 128, 0, s>>>(ctrl, cur, g.m, n);
+        k_bfs_decide<<<1, 128, 0, s>>>(ctrl, stripes, cur, g.m, n);
         GCONN_LAUNCHED("k_bfs_decide");
         // bottom-up: the frontier as bits (from the queue if it was one)
         k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, 1);
@@ -2516,15 +2573,15 @@ struct Run {
         k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[nxt], words, ctrl, 0);
         GCONN_LAUNCHED("k_bfs_clear_bits");
         k_bfs_bu<OffT><<<bu_grid, kBuBlock, 0, s>>>(off, g.nbrs, n, visited, bits[cur],
-                                                    bits[nxt], ctrl, nxt, fu, fv);
+                                                    bits[nxt], ctrl, stripes, nxt, fu, fv);
         GCONN_LAUNCHED("k_bfs_bu");
         // top-down: the frontier as a queue (from the bits if it was those)
         k_bits_to_queue<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
         GCONN_LAUNCHED("k_bits_to_queue");
         k_bfs_td_split<OffT><<<fixed, block, 0, s>>>(off, queue[cur], ctrl, cur, wl);
         GCONN_LAUNCHED("k_bfs_td_split");
-        k_bfs_td<OffT><<<td_grid, 256, 0, s>>>(off, g.nbrs, wl, ctrl, nxt, visited, queue[nxt],
-                                               fu, fv);
+        k_bfs_td<OffT><<<td_grid, 256, 0, s>>>(off, g.nbrs, wl, ctrl, stripes, nxt, visited,
+                                               queue[nxt], fu, fv);
         GCONN_LAUNCHED("k_bfs_td");
       }
       uint32_t mode = 0;
@@ -2918,6 +2975,7 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
     L.fr_bits1 = take(4 * words);
     L.queue0 = take(4 * n);
     L.queue1 = take(4 * n);
+    L.bfs_stripes = take(2 * kBfsStripes * sizeof(BfsStripe));
   }
   L.total = at;
   return L;
