@@ -1148,6 +1148,11 @@ template <typename OffT>
 __global__ void k_compress_gather(const OffT* __restrict__ off, uint32_t* P, uint32_t n, Ctrl* c,
                                   WorkLists wl, int mode, int skip_lmax, int want_stats) {
   const uint32_t lmax = skip_lmax ? c->lmax : kEmpty;
+  // L_max is the root of the largest sampled tree (k_lmax found it by walking
+  // to roots, and no link runs between sampling and this pass), so a chase
+  // that reaches it stops there without reading its slot: that one word
+  // would otherwise be read by almost every wave of the launch
+  const uint32_t known_root = c->lmax;
   // 16-byte loads of a lane's four offsets and parents when they are aligned
   // (uint32 offsets, 16-byte aligned arrays, four vertices in range).
   const bool vec = sizeof(OffT) == 4 &&
@@ -1190,8 +1195,9 @@ __global__ void k_compress_gather(const OffT* __restrict__ off, uint32_t* P, uin
         if (lane() == 0) GCONN_COUNT(kOpChaseRounds);  // diagnostic builds: one per wave round
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          if (r[k] != v0 + k && v0 + k < n) GCONN_COUNT(kOpChase);
-          q[k] = (r[k] != v0 + k && v0 + k < n) ? P[r[k]] : r[k];
+          const bool walk = r[k] != v0 + k && r[k] != known_root && v0 + k < n;
+          if (walk) GCONN_COUNT(kOpChase);
+          q[k] = walk ? P[r[k]] : r[k];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k)
