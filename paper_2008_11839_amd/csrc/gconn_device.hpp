@@ -109,9 +109,9 @@ __device__ __forceinline__ void wl_push(const WorkLists& wl, Ctrl* c, uint64_t g
   const bool md = active && deg > kSmallDeg && deg <= kMedDeg;
   const bool lg = active && deg > kMedDeg;
   bool any;
-  uint32_t slot = wave_append(&c->small_cnt[r], sm, &any);
+  uint32_t slot = wave_append(&c->small_cnt[r * kCntPad], sm, &any);
   if (sm) wl.small[(size_t)r * wl.cap + slot] = v;
-  slot = wave_append(&c->medium_cnt[r], md, &any);
+  slot = wave_append(&c->medium_cnt[r * kCntPad], md, &any);
   if (md) wl.medium[(size_t)r * wl.cap + slot] = v;
   if (__ballot(lg)) {
     const uint32_t nseg = lg ? (uint32_t)((deg + kSeg - 1) / kSeg) : 0u;
@@ -125,7 +125,7 @@ __device__ __forceinline__ void wl_push(const WorkLists& wl, Ctrl* c, uint64_t g
 __device__ __forceinline__ void wl_prefix(const uint32_t* cnt, uint32_t* pre) {
   if (threadIdx.x < 64) {
     uint32_t total;
-    const uint32_t x = cnt[lane()];
+    const uint32_t x = cnt[lane() * kCntPad];
     pre[lane()] = wave_exclusive(x, &total);
     if (lane() == 0) pre[kSubLists] = total;
   }

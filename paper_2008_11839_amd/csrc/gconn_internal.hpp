@@ -22,6 +22,7 @@ constexpr uint32_t kSmallDeg = 32;
 constexpr uint32_t kMedDeg = 1024;
 constexpr uint32_t kSeg = 1024;
 constexpr uint32_t kSubLists = 64;
+constexpr uint32_t kCntPad = 32;      // words between two work-list counters
 constexpr uint32_t kMaxLmaxSamples = 4096;
 constexpr int kRoundsPerSync = 8;        // device-side early-exit rounds per host check
 constexpr uint32_t kRoundSlots = 64;     // ring of per-round "changed" flags
@@ -47,8 +48,11 @@ struct Ctrl {
   unsigned long long stat_active;
   unsigned long long stat_finish_edges;
   unsigned long long stat_hooks;
-  uint32_t small_cnt[kSubLists];
-  uint32_t medium_cnt[kSubLists];
+  // work-list counters, one 128-byte line each: atomics on words of one line
+  // are performed one after another, so packed counters would serialise the
+  // appends of every wave in the launch
+  uint32_t small_cnt[kSubLists * kCntPad];
+  uint32_t medium_cnt[kSubLists * kCntPad];
   uint32_t changed[kRoundSlots];
   uint32_t kx_queue[8];               // XCD-bucketed k-out: per-XCD work-item cursors
   // BFS sampling, decided on the device level by level

@@ -1691,8 +1691,8 @@ __global__ void k_bfs_decide(Ctrl* c, BfsStripe* st, uint32_t cur, uint64_t m, u
   if (!run) return;
   const uint32_t nxt = cur ^ 1u;
   for (uint32_t i = threadIdx.x; i < kSubLists; i += blockDim.x) {
-    c->small_cnt[i] = 0;
-    c->medium_cnt[i] = 0;
+    c->small_cnt[i * kCntPad] = 0;
+    c->medium_cnt[i * kCntPad] = 0;
   }
   if (threadIdx.x == 0) {
     c->frontier_count[nxt] = 0;
@@ -1712,8 +1712,8 @@ __global__ void k_bfs_clear_bits(uint32_t* bits, uint32_t words, const Ctrl* c, 
 __global__ void k_bfs_level_reset(Ctrl* c, uint32_t nxt) {
   if (blockIdx.x != 0) return;
   for (uint32_t i = threadIdx.x; i < kSubLists; i += blockDim.x) {
-    c->small_cnt[i] = 0;
-    c->medium_cnt[i] = 0;
+    c->small_cnt[i * kCntPad] = 0;
+    c->medium_cnt[i * kCntPad] = 0;
   }
   if (threadIdx.x == 0) {
     c->frontier_count[nxt] = 0;
