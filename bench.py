@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "static CC Gedges/s on RMAT-24 (% HBM roofline); incremental updates/s + p99"
 KERNEL_SOURCES = ["paper_2008_11839_amd/csrc/gconn_static.hip",
-                  "paper_2008_11839_amd/csrc/gconn_rules.hpp"]
+                  "paper_2008_11839_amd/csrc/gconn_rules.hpp",
+                  "paper_2008_11839_amd/csrc/gconn_device.hpp",
+                  "paper_2008_11839_amd/csrc/gconn_internal.hpp"]
 # phase -> kernel launched in it (single-kernel phases)
 PHASE_KERNEL = {"init_ms": "k_init", "sample_ms": "k_sample_kout_pf", "lmax_ms": "k_lmax",
                 "gather_ms": "k_compress_gather", "finish_ms": "k_finish",
@@ -822,6 +824,101 @@ def mixed_bench(G, args) -> dict:
     return out
 
 
+# ---------------------------------------------------------------- profile summaries
+# rocprofv3 --output-format csv writes <dir>/**/<name>_kernel_trace.csv and
+# <dir>/**/<name>_counter_collection.csv; these turn them into the tables kept
+# under profiles/ (and the calibrated traffic record read above).
+
+def _prof_csv(d: str, suffix: str) -> list:
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _short_kernel(name: str) -> str:
+    import re
+    name = re.sub(r"^void ", "", name).replace("(anonymous namespace)::", "")
+    return re.sub(r"\(.*", "", name).replace("gconn::", "")
+
+
+def _base_kernel(name: str) -> str:
+    return _short_kernel(name).split("<")[0]
+
+
+def summarize_trace(d: str) -> str:
+    import statistics
+    per = {}
+    for r in _prof_csv(d, "kernel_trace.csv"):
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        per.setdefault(_short_kernel(r["Kernel_Name"]), []).append(us)
+    out = ["| kernel | calls | avg us (excl. 1st) | median us | min us | 1st call us |",
+           "|---|---|---|---|---|---|"]
+    for nm, ds in sorted(per.items(), key=lambda kv: -sum(kv[1][1:] or kv[1])):
+        rest = ds[1:] or ds
+        out.append(f"| `{nm}` | {len(ds)} | {sum(rest) / len(rest):.1f} | "
+                   f"{statistics.median(rest):.1f} | {min(rest):.1f} | {ds[0]:.1f} |")
+    return "\n".join(out)
+
+
+def _pmc_means(d: str) -> dict:
+    per = {}
+    for r in _prof_csv(d, "counter_collection.csv"):
+        c = per.setdefault(_short_kernel(r["Kernel_Name"]), {})
+        c.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} | {"_n": len(next(iter(cs.values())))}
+            for k, cs in per.items()}
+
+
+def summarize_pmc(d: str) -> str:
+    per = _pmc_means(d)
+    names = sorted({c for cs in per.values() for c in cs if c != "_n"})
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |",
+           "|---|---|" + "---|" * len(names)]
+    for nm, cs in per.items():
+        out.append(f"| `{nm}` | {cs['_n']} | " +
+                   " | ".join(f"{cs[c]:,.0f}" if c in cs else "" for c in names) + " |")
+    return "\n".join(out)
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str) -> str:
+    """Calibrated HBM bytes per dispatch from one FETCH_SIZE and one WRITE_SIZE
+    pass over --traffic-workload: the three 1 GiB add kernels read and write
+    exactly 1 GiB each, which fixes the scale of either counter; the record is
+    written to profiles/traffic_rmat24.txt with the kernel sources' hash."""
+    fe, wr = _pmc_means(fetch_dir), _pmc_means(write_dir)
+    copy = [k for k in fe if "add" in k.lower() and "elementwise" in k.lower()]
+    if not copy:
+        raise SystemExit("no calibration copy kernel in the FETCH_SIZE pass")
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / fe[copy[0]]["FETCH_SIZE"]
+    wscale = gib_kib / wr[copy[0]]["WRITE_SIZE"]
+    rows, per_kernel = [], {}
+    for k in fe:
+        if k in copy or "elementwise" in k or k not in wr:
+            continue
+        f, w = fe[k]["FETCH_SIZE"], wr[k]["WRITE_SIZE"]
+        b = int(round((f * fscale + w * wscale) * 1024))
+        per_kernel[_base_kernel(k)] = b
+        rows.append(f"| `{k}` | {f:.1f} | {w:.1f} | {b:,} |")
+    dom = PHASE_KERNEL["sample_ms"]
+    rec = {"source_sha": source_sha(), "kernel": dom,
+           "hbm_bytes_per_launch": per_kernel.get(dom), "fetch_scale": round(fscale, 5),
+           "write_scale": round(wscale, 5), "per_kernel_bytes": per_kernel}
+    with open(os.path.join(ROOT, "profiles", "traffic_rmat24.txt"), "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    head = (f"Calibration: the copy kernel reads and writes 1 GiB (1,048,576 KiB) per dispatch; "
+            f"FETCH_SIZE reads {fe[copy[0]]['FETCH_SIZE']:.0f} KiB and WRITE_SIZE "
+            f"{wr[copy[0]]['WRITE_SIZE']:.0f} KiB for it, so FETCH_SIZE is scaled by "
+            f"{fscale:.4f} and WRITE_SIZE by {wscale:.4f}.\n\n")
+    return head + "\n".join(["| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | "
+                              "calibrated HBM bytes/dispatch |", "|---|---|---|---|"] + rows)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -874,7 +971,23 @@ def main() -> int:
                     help="only run the workload the HBM-counter passes profile: three static CC "
                          "runs of the benchmark configuration, then three 1 GiB copies that "
                          "calibrate the counters")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="no GPU work: print a markdown table of rocprofv3 CSV output -- "
+                         "'trace DIR', 'pmc DIR', or 'traffic FETCH_DIR WRITE_DIR' (which also "
+                         "writes profiles/traffic_rmat24.txt)")
     args = ap.parse_args()
+
+    if args.summarize:
+        kind, dirs = args.summarize[0], args.summarize[1:]
+        if kind == "trace" and len(dirs) == 1:
+            print(summarize_trace(dirs[0]))
+        elif kind == "pmc" and len(dirs) == 1:
+            print(summarize_pmc(dirs[0]))
+        elif kind == "traffic" and len(dirs) == 2:
+            print(summarize_traffic(dirs[0], dirs[1]))
+        else:
+            ap.error("--summarize trace DIR | pmc DIR | traffic FETCH_DIR WRITE_DIR")
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the method runs on "
