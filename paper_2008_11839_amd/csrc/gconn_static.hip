@@ -1392,6 +1392,11 @@ __global__ void k_round_begin(Ctrl* c, uint32_t r) {
 __device__ __forceinline__ void mark_changed(Ctrl* c, uint32_t slot) {
   __hip_atomic_store(&c->changed[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// One flag store per workgroup (every thread of the block must call it):
+// write-throughs of one word from every wave of a launch queue at the L2.
+__device__ __forceinline__ void block_mark_changed(Ctrl* c, uint32_t slot, bool any) {
+  if (__syncthreads_or(any) && threadIdx.x == 0) mark_changed(c, slot);
+}
 
 // Shiloach-Vishkin round (Appendix A.3): for each edge, the larger of the two
 // labels, if it was a root at the start of the round, is lowered to the
@@ -1413,7 +1418,7 @@ __global__ void k_sv_round(const uint32_t* __restrict__ esrc, const uint32_t* __
       any = true;
     }
   }
-  if (any) mark_changed(c, slot);
+  block_mark_changed(c, slot, any);
 }
 
 // Forest edge for SV: an edge whose round-start labels are {l, h} and whose
@@ -1451,7 +1456,7 @@ __global__ void k_shortcut_full(Ctrl* c, uint32_t* P, uint32_t* prev, uint32_t n
     }
     if (prev) prev[v] = r;
   }
-  if (count_change && any) mark_changed(c, slot);
+  block_mark_changed(c, slot, count_change && any);
 }
 
 // Liu-Tarjan Shortcut: one pointer-jumping step, P[v] = P[P[v]].
@@ -1467,7 +1472,7 @@ __global__ void k_shortcut_one(Ctrl* c, uint32_t* P, uint32_t* prev, uint32_t n,
     }
     if (prev) prev[v] = ld(&P[v]);
   }
-  if (any) mark_changed(c, slot);
+  block_mark_changed(c, slot, any);
 }
 
 // Liu-Tarjan connect + update (Appendix A.4) with in-place atomic minimum:
@@ -1504,7 +1509,7 @@ __global__ void k_lt_round(const uint32_t* __restrict__ esrc, const uint32_t* __
       }
     }
   }
-  if (any) mark_changed(c, slot);
+  block_mark_changed(c, slot, any);
 }
 
 // Liu-Tarjan Alter: replace each edge by the edge between its endpoints'
@@ -1527,7 +1532,7 @@ __global__ void k_lt_alter(uint32_t* esrc, uint32_t* edst, Ctrl* c, const uint32
       any = true;
     }
   }
-  if (any) mark_changed(c, slot);
+  block_mark_changed(c, slot, any);
 }
 
 // Label propagation round: across an edge with different labels the larger
@@ -1566,7 +1571,7 @@ __global__ void k_lp_round(const uint32_t* __restrict__ esrc, const uint32_t* __
       if (amin(&P[tv], lu) > lu) any = true;
     }
   }
-  if (any) mark_changed(c, slot);
+  block_mark_changed(c, slot, any);
 }
 
 template <typename OffT>
