@@ -1318,6 +1318,8 @@ __global__ void k_unite_pairs(const uint32_t* __restrict__ a, const uint32_t* __
 // --------------------------------------------------------------- materialised edges
 // SV, LT and LP iterate over the active edges many times; they are laid out
 // once as a COO pair list (one entry per CSR entry of an active vertex).
+constexpr uint32_t kMatChunks = 16;
+
 template <typename OffT>
 __global__ void k_materialize(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs,
                               WorkLists wl, Ctrl* c, uint32_t* esrc, uint32_t* edst) {
@@ -1326,23 +1328,40 @@ __global__ void k_materialize(const OffT* __restrict__ off, const uint32_t* __re
   wl_prefix(c->medium_cnt, pre_m);
   __syncthreads();
   const uint32_t S = pre_s[kSubLists], M = pre_m[kSubLists], G = c->seg_count;
-  for (uint64_t base = wave_base(); base < S; base += wave_stride()) {
-    const uint64_t i = base + lane();
-    uint32_t u = 0, deg = 0;
-    uint64_t b = 0;
-    if (i < S) {
-      u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
-      b = off[u];
-      deg = (uint32_t)((uint64_t)off[u + 1] - b);
+  // Small vertices: a wave takes kMatChunks groups of 64 list entries and
+  // reserves their edges with one atomic (a reservation per 64 entries put one
+  // single-address atomic per wave of the launch in one L2 queue): the first
+  // pass adds up the degrees, the second writes the edges.
+  for (uint64_t base = wave_base() * kMatChunks; base < S;
+       base += wave_stride() * kMatChunks) {
+    unsigned long long mine = 0;
+    for (uint32_t k = 0; k < kMatChunks; ++k) {
+      const uint64_t i = base + (uint64_t)k * 64 + lane();
+      if (i < S) {
+        const uint32_t u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
+        mine += (uint64_t)off[u + 1] - off[u];
+      }
     }
-    uint32_t total;
-    const uint32_t o = wave_exclusive(deg, &total);
+    const unsigned long long all = wave_sum(mine);
     unsigned long long pos = 0;
-    if (total && lane() == 0) pos = atomicAdd(&c->edge_count, (unsigned long long)total);
-    pos = __shfl(pos, 0) + o;
-    for (uint32_t j = 0; j < deg; ++j) {
-      esrc[pos + j] = u;
-      edst[pos + j] = nbrs[b + j];
+    if (all && lane() == 0) pos = atomicAdd(&c->edge_count, all);
+    pos = __shfl(pos, 0);
+    for (uint32_t k = 0; k < kMatChunks; ++k) {
+      const uint64_t i = base + (uint64_t)k * 64 + lane();
+      uint32_t u = 0, deg = 0;
+      uint64_t b = 0;
+      if (i < S) {
+        u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
+        b = off[u];
+        deg = (uint32_t)((uint64_t)off[u + 1] - b);
+      }
+      uint32_t total;
+      const uint32_t o = wave_exclusive(deg, &total);
+      for (uint32_t j = 0; j < deg; ++j) {
+        esrc[pos + o + j] = u;
+        edst[pos + o + j] = nbrs[b + j];
+      }
+      pos += total;
     }
   }
   for (uint64_t w = wave_index(); w < (uint64_t)M + G; w += wave_count()) {
