@@ -156,3 +156,20 @@ def test_grid_automatic_schedule(grid3m, cfg):
     assert np.array_equal(G.to_u32(lab), want)
     oracle.check_forest(C.n, C.offsets, C.nbrs, fu, fv, want)
     assert np.array_equal(fu != G.EMPTY, want != np.arange(C.n, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("cfg", [dict(link="sv"), dict(link="lt", lt_variant="PRF"),
+                                 dict(link="lt", lt_variant="EUSA")],
+                         ids=lambda c: "-".join(c.values()))
+def test_grid_unsampled_rounds(grid3m, cfg):
+    """SV and Liu-Tarjan without sampling on the 3.1 M-vertex mesh: every
+    vertex is active, so the edge layout for the rounds reserves many
+    1,024-entry groups per wave; labels equal the oracle's."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    C, dg, want = grid3m
+    say(f"[grid unsampled] {cfg}")
+    lab, st = G.cc(dg, options=G.Options(sample="none", **cfg), stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(G.to_u32(lab), want), cfg
+    assert st["finish_edges"] == C.m
