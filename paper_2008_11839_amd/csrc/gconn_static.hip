@@ -3054,7 +3054,7 @@ gconn_status run_static(const gconn_graph& g, uint32_t* P, uint32_t* fu, uint32_
     k_ctrl_init<<<1, 256, 0, s>>>(run.ctrl);
     GCONN_LAUNCHED("k_ctrl_init");
   } else {
-    // the automatic k-out schedule's locality probe rides in block 0
+    // the automatic k-out schedule's locality probe rides in blocks 1-16
     KoutProbe probe{};
     const uint32_t init_grid = grid_for(std::max<uint64_t>(vec ? n / 4 : n, 1), block);
     if (g.format == GCONN_CSR && n > 0 && g.m > 0 && kout_auto_local_applies(o) &&
