@@ -82,20 +82,58 @@ __global__ void k_batch_sample(const uint64_t* __restrict__ off, const uint32_t*
   const uint64_t tiles = ((uint64_t)n + 63) >> 6;
   uint64_t span = 1;
   while (span < tiles) span <<= 1;
-  for (uint64_t t = wave_index(); t < span; t += wave_count()) {
-    const uint64_t tile = (t * 0x9E3779B97F4A7C15ull) & (span - 1);
-    if (tile >= tiles) continue;  // uniform over the wave
-    const uint64_t base = tile << 6;
-    const BatchClass& bc = class_of(cl, graph_class, tile_graph[tile]);
-    if (!bc.sample) continue;  // uniform over the wave: one graph per tile
-    const uint64_t v = base + lane();
-    const uint64_t b = off[v], deg = off[v + 1] - b;
-    uint32_t take = (uint32_t)(deg < bc.k ? deg : bc.k);
-    // hook-based step 2: only the vertices step 1 left as roots (degree 0, or
-    // first neighbour not smaller -- decided from the graph, not from P)
-    if (bc.sample == 2 && (deg == 0 || nbrs[b] < v)) take = 0;
-    for (uint32_t j = 0; j < take; ++j) unite_by_id(bc.rule, lc, (uint32_t)v, nbrs[b + j]);
-    sampled += take;
+  constexpr uint64_t kNoTile = ~0ull;
+  uint64_t t = wave_index();
+  // next tile of this wave in the scrambled order (uniform over the wave)
+  auto advance = [&]() -> uint64_t {
+    while (t < span) {
+      const uint64_t tile = (t * 0x9E3779B97F4A7C15ull) & (span - 1);
+      t += wave_count();
+      if (tile < tiles) return tile;
+    }
+    return kNoTile;
+  };
+  // a tile's graph, the lane's row bounds and first two neighbours: loaded for
+  // the next tile before the current tile's unions run, so that they are in
+  // flight together (the batch's n is a multiple of 64: every lane's vertex
+  // exists, padding vertices have empty rows)
+  struct Row {
+    uint64_t b, d;
+    uint32_t w0, w1, g;
+  };
+  auto fetch = [&](uint64_t tile, Row& r) {
+    r.b = r.d = 0;
+    r.w0 = r.w1 = r.g = 0;
+    if (tile == kNoTile) return;
+    const uint64_t v = (tile << 6) + lane();
+    r.g = tile_graph[tile];
+    r.b = off[v];
+    r.d = off[v + 1] - r.b;
+    if (r.d > 0) r.w0 = nbrs[r.b];
+    if (r.d > 1) r.w1 = nbrs[r.b + 1];
+  };
+  uint64_t cur = advance();
+  Row rc;
+  fetch(cur, rc);
+  while (cur != kNoTile) {
+    const uint64_t nxt = advance();
+    Row rn;
+    fetch(nxt, rn);
+    const BatchClass& bc = class_of(cl, graph_class, rc.g);
+    if (bc.sample) {  // uniform over the wave: one graph per tile
+      const uint64_t v = (cur << 6) + lane();
+      uint32_t take = (uint32_t)(rc.d < bc.k ? rc.d : bc.k);
+      // hook-based step 2: only the vertices step 1 left as roots (degree 0,
+      // or first neighbour not smaller -- decided from the graph, not from P)
+      if (bc.sample == 2 && (rc.d == 0 || rc.w0 < v)) take = 0;
+      for (uint32_t j = 0; j < take; ++j) {
+        const uint32_t w = j == 0 ? rc.w0 : j == 1 ? rc.w1 : nbrs[rc.b + j];
+        unite_by_id(bc.rule, lc, (uint32_t)v, w);
+      }
+      sampled += take;
+    }
+    cur = nxt;
+    rc = rn;
   }
   if (stats) {
     sampled = wave_sum(sampled);
