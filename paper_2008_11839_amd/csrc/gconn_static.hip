@@ -1683,21 +1683,32 @@ __global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* vis
 // integers -- note which representation change the level needs first, and
 // clear the counters of frontier `nxt`.  Every later kernel of the level
 // reads bfs_mode and returns at once when the level is not its kind.
-__global__ void k_bfs_decide(Ctrl* c, BfsStripe* st, uint32_t cur, uint64_t m, uint32_t n) {
-  __shared__ uint32_t run;
-  if (threadIdx.x < 64) {
-    // fold the stripes of frontier `cur` into its counters (wave 0)
-    BfsStripe* t = st + cur * kBfsStripes + threadIdx.x;
-    unsigned long long sc = t->count, se = t->edges;
-    t->count = t->edges = 0;
-    sc = wave_sum(sc);
-    se = wave_sum(se);
-    if (threadIdx.x == 0 && (sc || se)) {
-      c->frontier_count[cur] += (uint32_t)sc;
-      c->frontier_edges[cur] += se;
-      c->explored_edges += se;
-    }
+// Fold the stripes of frontier `cur` into its counters (threads 0..63, one
+// wave).
+__device__ __forceinline__ void bfs_fold(Ctrl* c, BfsStripe* st, uint32_t cur) {
+  BfsStripe* t = st + cur * kBfsStripes + threadIdx.x;
+  unsigned long long sc = t->count, se = t->edges;
+  t->count = t->edges = 0;
+  sc = wave_sum(sc);
+  se = wave_sum(se);
+  if (threadIdx.x == 0 && (sc || se)) {
+    c->frontier_count[cur] += (uint32_t)sc;
+    c->frontier_edges[cur] += se;
+    c->explored_edges += se;
   }
+}
+
+// The same fold on its own, so that the host can read the next frontier's
+// size at a check (launched with 64 threads).
+__global__ void k_bfs_fold(Ctrl* c, BfsStripe* st, uint32_t cur) { bfs_fold(c, st, cur); }
+
+// force_td: the host enqueued only the top-down kernels for this level (a
+// batch of levels whose frontier is far below the switch point), so the
+// level stays top-down whatever the rule would pick.
+__global__ void k_bfs_decide(Ctrl* c, BfsStripe* st, uint32_t cur, uint64_t m, uint32_t n,
+                             int force_td) {
+  __shared__ uint32_t run;
+  if (threadIdx.x < 64) bfs_fold(c, st, cur);
   if (threadIdx.x == 0) {
     const uint32_t count = c->frontier_count[cur];
     run = c->bfs_mode != 0 && count != 0;
@@ -1709,6 +1720,7 @@ __global__ void k_bfs_decide(Ctrl* c, BfsStripe* st, uint32_t cur, uint64_t m, u
       bool bu = c->bfs_mode == 2;
       if (!bu && 14 * m_f > m_u) bu = true;
       else if (bu && 24ull * count < n) bu = false;
+      if (force_td) bu = false;
       const bool q = c->bfs_as_queue != 0;
       c->bfs_convert = bu ? (q ? 1u : 0u) : (q ? 0u : 2u);
       c->bfs_mode = bu ? 2u : 1u;
@@ -2595,35 +2607,63 @@ struct Run {
     const uint32_t wgrid = std::min<uint32_t>(gridN(words), kPersistentBlocks);
     const uint32_t bu_grid = (uint32_t)std::min<uint64_t>(
         ((uint64_t)n / 4 + kBuBlock) / kBuBlock, kPersistentBlocks);
+    // A batch whose frontier starts as a top-down queue far below the point
+    // where the rule would turn bottom-up (edges x 14 x 64 under the
+    // unexplored edges) enqueues only the top-down kernels: a high-diameter
+    // graph runs thousands of small top-down levels, where the bottom-up
+    // kernels' launches, each returning at once, would be most of the time.
+    // Such a batch also sizes the top-down grids to the frontier it starts
+    // from (both kernels loop over their work, so any grid is correct): a
+    // full grid spends more on starting its workgroups, and on each of them
+    // reading the work-list counters, than on a few thousand vertices.
+    bool td_only = false;
+    uint32_t small_grid = fixed, small_td_grid = td_grid;
     for (uint64_t level = 0;; level += kRoundsPerSync) {
       for (int j = 0; j < kRoundsPerSync; ++j) {
         const uint32_t cur = (uint32_t)((level + j) & 1), nxt = cur ^ 1;
-        k_bfs_decide<<<1, 128, 0, s>>>(ctrl, stripes, cur, g.m, n);
+        k_bfs_decide<<<1, 128, 0, s>>>(ctrl, stripes, cur, g.m, n, td_only ? 1 : 0);
         GCONN_LAUNCHED("k_bfs_decide");
-        // bottom-up: the frontier as bits (from the queue if it was one)
-        k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, 1);
-        GCONN_LAUNCHED("k_bfs_clear_bits");
-        k_queue_to_bits<<<fixed, block, 0, s>>>(queue[cur], ctrl, cur, bits[cur]);
-        GCONN_LAUNCHED("k_queue_to_bits");
-        k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[nxt], words, ctrl, 0);
-        GCONN_LAUNCHED("k_bfs_clear_bits");
-        k_bfs_bu<OffT><<<bu_grid, kBuBlock, 0, s>>>(off, g.nbrs, n, visited, bits[cur],
-                                                    bits[nxt], ctrl, stripes, nxt, fu, fv);
-        GCONN_LAUNCHED("k_bfs_bu");
-        // top-down: the frontier as a queue (from the bits if it was those)
-        k_bits_to_queue<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
-        GCONN_LAUNCHED("k_bits_to_queue");
-        k_bfs_td_split<OffT><<<fixed, block, 0, s>>>(off, queue[cur], ctrl, cur, wl);
+        if (!td_only) {
+          // bottom-up: the frontier as bits (from the queue if it was one)
+          k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, 1);
+          GCONN_LAUNCHED("k_bfs_clear_bits");
+          k_queue_to_bits<<<fixed, block, 0, s>>>(queue[cur], ctrl, cur, bits[cur]);
+          GCONN_LAUNCHED("k_queue_to_bits");
+          k_bfs_clear_bits<<<wgrid, block, 0, s>>>(bits[nxt], words, ctrl, 0);
+          GCONN_LAUNCHED("k_bfs_clear_bits");
+          k_bfs_bu<OffT><<<bu_grid, kBuBlock, 0, s>>>(off, g.nbrs, n, visited, bits[cur],
+                                                      bits[nxt], ctrl, stripes, nxt, fu, fv);
+          GCONN_LAUNCHED("k_bfs_bu");
+          // top-down: the frontier as a queue (from the bits if it was those)
+          k_bits_to_queue<<<wgrid, block, 0, s>>>(bits[cur], words, ctrl, queue[cur]);
+          GCONN_LAUNCHED("k_bits_to_queue");
+        }
+        k_bfs_td_split<OffT><<<td_only ? small_grid : fixed, block, 0, s>>>(off, queue[cur], ctrl,
+                                                                          cur, wl);
         GCONN_LAUNCHED("k_bfs_td_split");
-        k_bfs_td<OffT><<<td_grid, 256, 0, s>>>(off, g.nbrs, wl, ctrl, stripes, nxt, visited,
-                                               queue[nxt], fu, fv);
+        k_bfs_td<OffT><<<td_only ? small_td_grid : td_grid, 256, 0, s>>>(
+            off, g.nbrs, wl, ctrl, stripes, nxt, visited, queue[nxt], fu, fv);
         GCONN_LAUNCHED("k_bfs_td");
       }
-      uint32_t mode = 0;
-      GCONN_HIP(hipMemcpyAsync(&mode, &ctrl->bfs_mode, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               s));
+      const uint32_t next = (uint32_t)((level + kRoundsPerSync) & 1);
+      k_bfs_fold<<<1, 64, 0, s>>>(ctrl, stripes, next);
+      GCONN_LAUNCHED("k_bfs_fold");
+      Ctrl h;
+      GCONN_HIP(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
       GCONN_HIP(hipStreamSynchronize(s));
+      const uint32_t mode = h.bfs_mode;
       if (mode == 0) break;
+      const uint64_t unexplored = g.m > h.explored_edges ? g.m - h.explored_edges : 0;
+      td_only = mode == 1 && h.bfs_as_queue != 0 &&
+                (unsigned __int128)h.frontier_edges[next] * 14 * 64 <= unexplored;
+      if (td_only) {
+        // a lane per frontier vertex and four row entries per lane, with
+        // room for the frontier to grow 8x over the batch
+        const uint64_t cnt = h.frontier_count[next], edges = h.frontier_edges[next];
+        const uint64_t lanes = std::max<uint64_t>(cnt, edges / 4) * 8;
+        small_grid = (uint32_t)std::min<uint64_t>(fixed, std::max<uint64_t>(8, lanes / block + 1));
+        small_td_grid = (uint32_t)std::min<uint64_t>(td_grid, std::max<uint64_t>(8, lanes / 256 + 1));
+      }
       if (level + kRoundsPerSync > (uint64_t)n + kRoundsPerSync)
         return fail(GCONN_EDEVICE, "BFS did not finish within n levels");
     }
