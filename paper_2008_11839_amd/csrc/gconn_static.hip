@@ -1332,10 +1332,13 @@ __global__ void k_materialize(const OffT* __restrict__ off, const uint32_t* __re
   // reserves their edges with one atomic (a reservation per 64 entries put one
   // single-address atomic per wave of the launch in one L2 queue): the first
   // pass adds up the degrees, the second writes the edges.
-  for (uint64_t base = wave_base() * kMatChunks; base < S;
-       base += wave_stride() * kMatChunks) {
+  // (fewer groups per wave when the list is short, so that every wave has some)
+  const uint64_t W = wave_count();
+  const uint32_t chunks = (uint32_t)std::min<uint64_t>(
+      kMatChunks, std::max<uint64_t>(1, (S + 64 * W - 1) / (64 * W)));
+  for (uint64_t base = wave_base() * chunks; base < S; base += wave_stride() * chunks) {
     unsigned long long mine = 0;
-    for (uint32_t k = 0; k < kMatChunks; ++k) {
+    for (uint32_t k = 0; k < chunks; ++k) {
       const uint64_t i = base + (uint64_t)k * 64 + lane();
       if (i < S) {
         const uint32_t u = wl_get(wl.small, wl.cap, pre_s, (uint32_t)i);
@@ -1346,7 +1349,7 @@ __global__ void k_materialize(const OffT* __restrict__ off, const uint32_t* __re
     unsigned long long pos = 0;
     if (all && lane() == 0) pos = atomicAdd(&c->edge_count, all);
     pos = __shfl(pos, 0);
-    for (uint32_t k = 0; k < kMatChunks; ++k) {
+    for (uint32_t k = 0; k < chunks; ++k) {
       const uint64_t i = base + (uint64_t)k * 64 + lane();
       uint32_t u = 0, deg = 0;
       uint64_t b = 0;
@@ -1432,7 +1435,11 @@ __global__ void k_sv_round(const uint32_t* __restrict__ esrc, const uint32_t* __
     uint32_t pu = snapshot ? prev[u] : ld(&P[u]);
     uint32_t pv = snapshot ? prev[v] : ld(&P[v]);
     uint32_t l = pu < pv ? pu : pv, h = pu < pv ? pv : pu;
-    if (l != h && prev[h] == h) {
+    // the atomic only when it can lower the slot: once a component's root
+    // holds its final label, the many edges into it would otherwise all queue
+    // on that one word (a read may be stale, but P only decreases, so a
+    // stale value is never below the current one)
+    if (l != h && prev[h] == h && ld(&P[h]) > l) {
       amin(&P[h], l);
       any = true;
     }
@@ -1502,6 +1509,7 @@ __global__ void k_shortcut_one(Ctrl* c, uint32_t* P, uint32_t* prev, uint32_t n,
 __device__ __forceinline__ bool lt_send(uint32_t* P, const uint32_t* prev, uint32_t to,
                                         uint32_t val, int root_update) {
   if (root_update && prev[to] != to) return false;
+  if (ld(&P[to]) <= val) return false;  // cannot lower it (P only decreases)
   return amin(&P[to], val) > val;
 }
 
