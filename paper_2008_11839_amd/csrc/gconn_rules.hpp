@@ -211,12 +211,16 @@ GCONN_HD uint32_t find(uint32_t* P, uint32_t u, bool ac, uint32_t pu = kEmpty) {
       u = shortcut(&P[u], e, w, ac) ? w : e;  // the new P[u], smaller than u either way
     }
   } else {  // kFindCompress
-    uint32_t r = u;
+    uint32_t r = u, first = kEmpty;
     for (;;) {
       uint32_t p = ld(&P[r]);
+      if (first == kEmpty) first = p;
       if (p == r) break;
       r = p;
     }
+    // u is the root or points at it already: no atomic on its slot (a hub's
+    // slot would take one from every find that starts there)
+    if (first == r) return r;
     uint32_t x = u;
     while (x != r) {
       uint32_t old = amin(&P[x], r);
