@@ -433,19 +433,33 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
   if (threadIdx.x == 0) nrec = 0;
   __syncthreads();
   unsigned long long sampled = 0, linked = 0;
-  // Each lane takes four consecutive vertices per step and loads their row
-  // bounds and leading neighbours (up to eight loads) before any union runs.
-  for (uint32_t i0 = 4 * threadIdx.x; i0 < len; i0 += 4 * blockDim.x) {
-    uint64_t o[5];
+  // Each lane takes four consecutive vertices per step.  Their row bounds
+  // are loaded two steps ahead and their leading neighbours one step ahead,
+  // so both are in flight while the current step's LDS unions run.
+  const uint32_t stride = 4 * blockDim.x;
+  auto load_bounds = [&](uint32_t i, uint64_t (&o)[5]) {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] = i0 + j <= len ? (uint64_t)off[lo + i0 + j] : 0;
-    uint32_t wv[8];
+    for (int j = 0; j < 5; ++j) o[j] = i + j <= len ? (uint64_t)off[lo + i + j] : 0;
+  };
+  auto load_heads = [&](uint32_t i, const uint64_t (&o)[5], uint32_t (&w)[8]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const uint64_t d = i0 + j < len ? o[j + 1] - o[j] : 0;
-      wv[2 * j] = d > 0 ? nbrs[o[j]] : kEmpty;
-      wv[2 * j + 1] = (d > 1 && k > 1) ? nbrs[o[j] + 1] : kEmpty;
+      const uint64_t d = i + j < len ? o[j + 1] - o[j] : 0;
+      w[2 * j] = d > 0 ? nbrs[o[j]] : kEmpty;
+      w[2 * j + 1] = (d > 1 && k > 1) ? nbrs[o[j] + 1] : kEmpty;
     }
+  };
+  uint64_t o[5], o1[5];
+  uint32_t wv[8];
+  uint32_t i0 = 4 * threadIdx.x;
+  load_bounds(i0, o);
+  load_heads(i0, o, wv);
+  load_bounds(i0 + stride, o1);
+  for (; i0 < len; i0 += stride) {
+    uint64_t o2[5];
+    uint32_t w1[8];
+    load_bounds(i0 + 2 * stride, o2);
+    load_heads(i0 + stride, o1, w1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t i = i0 + j;
@@ -490,6 +504,13 @@ __global__ void __launch_bounds__(1024) k_kout_local(const OffT* __restrict__ of
       }
       if (!local) res[v] = r;
     }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      o[j] = o1[j];
+      o1[j] = o2[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wv[j] = w1[j];
   }
   __syncthreads();
   if (local) {
