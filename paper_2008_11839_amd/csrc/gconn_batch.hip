@@ -63,10 +63,14 @@ __device__ __forceinline__ const BatchClass& class_of(const BatchClasses& cl,
   return cl.c[graph_class ? graph_class[g] : 0];
 }
 
-// tile t (64 vertices) -> graph id
+// tile t (64 vertices) -> graph id: a workgroup per graph writes its tiles
+// (one thread per graph took a sequential pass over a million-vertex graph's
+// 15,625 tiles)
 __global__ void k_batch_tiles(const uint32_t* __restrict__ vbase, uint32_t G, uint32_t* tile_graph) {
-  for (uint64_t g = gtid(); g < G; g += wave_stride())
-    for (uint32_t t = vbase[g] >> 6; t < (vbase[g + 1] >> 6); ++t) tile_graph[t] = (uint32_t)g;
+  for (uint32_t g = blockIdx.x; g < G; g += gridDim.x) {
+    const uint32_t lo = vbase[g] >> 6, hi = vbase[g + 1] >> 6;
+    for (uint32_t t = lo + threadIdx.x; t < hi; t += blockDim.x) tile_graph[t] = g;
+  }
 }
 
 __global__ void k_batch_sample(const uint64_t* __restrict__ off, const uint32_t* __restrict__ nbrs,
@@ -425,7 +429,8 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
   const uint32_t n = b->n, G = b->num_graphs, block = b->block ? b->block : 256;
 
   GCONN_TRY(reset_ctrl_and_parents(ctrl, P, n, s));
-  k_batch_tiles<<<grid_for(G, block), block, 0, s>>>(b->vbase, G, tiles);
+  k_batch_tiles<<<std::max<uint32_t>(1, std::min<uint32_t>(G, 65535)), 256, 0, s>>>(b->vbase, G,
+                                                                                   tiles);
   GCONN_LAUNCHED("k_batch_tiles");
   if (n > 0 && b->m > 0) {
     bool any_hb = false;
