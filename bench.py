@@ -4,16 +4,19 @@
 Workload (default): RMAT scale 24, edge factor 16, quadrant probabilities
 (0.57, 0.19, 0.19, 0.05), seeded id scramble, symmetrised CSR with sorted rows
 (n = 2^24, m = 536,865,446 directed entries), seed 1.  Method: k-out sampling
-(first k = 2 edges) + Union-Rem-CAS with SplitAtomicOne splicing and
-AtomicSplit compression, then finalisation -- one gconn_cc call per step, the
-graph already resident in HBM, parent-array initialisation included.
+(first k = 2 edges, automatic schedule) + Union-Rem-CAS with Rem's
+SpliceAtomic and AtomicSplit (FindSplit) compression, then finalisation --
+one gconn_cc call per step, the graph already resident in HBM, parent-array
+initialisation included.
 
 Prints ONE JSON line on stdout: throughput in Gedges/s (directed CSR entries
 per second), the roofline of the dominant kernel (algorithmic bytes over its
-HIP-event-timed duration, against 8 TB/s), the CPU oracle timed on the host,
-per-phase times, the spanning-forest throughput and an incremental
-(insert/query batch) measurement on the same graph's edge stream.
-Progress goes to stderr.
+HIP-event-timed duration, against 8 TB/s, beside the random-access ceilings
+measured in the same run), the CPU oracle timed on the host, per-phase
+times, and the extra legs: spanning forest, other seeds, union-find rules,
+samplers, the other configurations, mixed and incremental batches, the
+served request stream and the many-graph batch.  Progress goes to stderr.
+`--summarize` turns rocprofv3 CSV output into the tables kept in profiles/.
 """
 from __future__ import annotations
 
@@ -884,7 +887,7 @@ def summarize_pmc(d: str) -> str:
     return "\n".join(out)
 
 
-def summarize_traffic(fetch_dir: str, write_dir: str) -> str:
+def summarize_traffic(fetch_dir: str, write_dir: str, out: str | None = None) -> str:
     """Calibrated HBM bytes per dispatch from one FETCH_SIZE and one WRITE_SIZE
     pass over --traffic-workload: the three 1 GiB add kernels read and write
     exactly 1 GiB each, which fixes the scale of either counter; the record is
@@ -908,7 +911,7 @@ def summarize_traffic(fetch_dir: str, write_dir: str) -> str:
     rec = {"source_sha": source_sha(), "kernel": dom,
            "hbm_bytes_per_launch": per_kernel.get(dom), "fetch_scale": round(fscale, 5),
            "write_scale": round(wscale, 5), "per_kernel_bytes": per_kernel}
-    with open(os.path.join(ROOT, "profiles", "traffic_rmat24.txt"), "w") as f:
+    with open(out or os.path.join(ROOT, "profiles", "traffic_rmat24.txt"), "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
     head = (f"Calibration: the copy kernel reads and writes 1 GiB (1,048,576 KiB) per dispatch; "
