@@ -1624,16 +1624,22 @@ __global__ void k_lp_round(const uint32_t* __restrict__ esrc, const uint32_t* __
 
 template <typename OffT>
 __global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) {
+  // four consecutive vertices per lane: their five row bounds are loaded
+  // together, so a lane's iterations are not one dependent load each
   unsigned long long best = 0;
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    uint64_t v = base + lane();
-    unsigned long long key = 0;
-    if (v < n) {
-      uint64_t deg = (uint64_t)off[v + 1] - off[v];
+  for (uint64_t base = wave_base() * 4; base < n; base += wave_stride() * 4) {
+    const uint64_t v0 = base + 4 * lane();
+    uint64_t o[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] = v0 + j <= n ? (uint64_t)off[v0 + j] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (v0 + j >= n) break;
+      uint64_t deg = o[j + 1] - o[j];
       if (deg > 0xFFFFFFFEull) deg = 0xFFFFFFFEull;
-      key = ((deg + 1) << 32) | (0xFFFFFFFFull - v);
+      const unsigned long long key = ((deg + 1) << 32) | (0xFFFFFFFFull - (v0 + j));
+      best = key > best ? key : best;
     }
-    best = key > best ? key : best;
   }
   // every lane of a wave ran the same iterations, so all are active here;
   // then the workgroup's waves combine in LDS: one atomic per workgroup (the
@@ -2155,11 +2161,27 @@ __global__ void k_bfs_min(const uint32_t* __restrict__ visited, uint32_t words, 
   }
 }
 
+// Every slot is written, four per lane: a visited vertex gets the component
+// minimum, any other keeps its own id (no BFS kernel writes P before this, so
+// that is the value it holds); whole lines are written instead of scattered
+// words.
 __global__ void k_bfs_label(const uint32_t* __restrict__ visited, uint32_t n, const Ctrl* c,
                             uint32_t* P) {
   const uint32_t r = c->comp_min;
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += wave_stride())
-    if (visited[v >> 5] & (1u << (v & 31))) P[v] = r;
+  const bool vec = (reinterpret_cast<uintptr_t>(P) % 16) == 0;
+  for (uint64_t v0 = 4 * gtid(); v0 < n; v0 += 4 * wave_stride()) {
+    const uint32_t word = visited[v0 >> 5] >> (v0 & 31);
+    uint32_t q[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = (word >> j) & 1u ? r : (uint32_t)(v0 + j);
+    if (vec && v0 + 4 <= n) {
+      *reinterpret_cast<uint4*>(P + v0) = make_uint4(q[0], q[1], q[2], q[3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (v0 + j < n) P[v0 + j] = q[j];
+    }
+  }
 }
 
 // --------------------------------------------------------------- incremental
@@ -2621,7 +2643,8 @@ struct Run {
                           reinterpret_cast<uint32_t*>(ws + L.queue1)};
     k_fill<<<gridN(words), block, 0, s>>>(visited, 0u, words);
     GCONN_LAUNCHED("k_fill(visited)");
-    k_bfs_argmax<OffT><<<std::min<uint32_t>(gridN(n), 1024), block, 0, s>>>(off, n, ctrl);
+    k_bfs_argmax<OffT><<<std::min<uint32_t>(gridN((n + 3) / 4), 2048), block, 0, s>>>(off, n,
+                                                                                     ctrl);
     GCONN_LAUNCHED("k_bfs_argmax");
     BfsStripe* stripes = reinterpret_cast<BfsStripe*>(ws + L.bfs_stripes);
     k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0], stripes);
@@ -2705,7 +2728,7 @@ struct Run {
     }
     k_bfs_min<<<std::min<uint32_t>(gridN(words), 1024), block, 0, s>>>(visited, words, ctrl);
     GCONN_LAUNCHED("k_bfs_min");
-    k_bfs_label<<<gridN(n), block, 0, s>>>(visited, n, ctrl, P);
+    k_bfs_label<<<gridN((n + 3) / 4), block, 0, s>>>(visited, n, ctrl, P);
     GCONN_LAUNCHED("k_bfs_label");
     // the work lists were used as scratch: clear their counters
     k_bfs_level_reset<<<1, 128, 0, s>>>(ctrl, 0);
