@@ -521,6 +521,8 @@ def batched_bench(G, args) -> dict:
     G._check(G.lib().gconn_cc_batch_workspace_size(ctypes.byref(db.c), ctypes.byref(bb)))
     ws_b = G.alloc_workspace(bb.value)
     lab_b = torch.empty(hb.n, dtype=torch.int32, device="cuda")
+    # the launch's workgroup shape, timed on the whole batch
+    _, block_times = B.Autotuner.tune_batch_block(db, classes, lab_b, ws_b)
     # one launch sequence per graph: each graph resident with local ids
     dgs = [G.csr(g.offsets, g.nbrs, g.n) for g in graphs]
     opt1 = G.Options(sample="kout", link="rem_cas", find="split")
@@ -579,6 +581,7 @@ def batched_bench(G, args) -> dict:
             "graphs": len(graphs), "n": total_n, "m_directed": total_m,
             "classes": {k: tuner.table[k]["choice"] for k in sorted(set(keys))},
             "batch_block": batch_block,
+            "batch_block_ms": {str(k): round(v, 3) for k, v in block_times.items()},
             "batched_ms": round(t_batch * 1e3, 3), "batched_captured_ms": round(t_cap * 1e3, 3),
             "per_graph_launches_ms": round(t_loop * 1e3, 3),
             "speedup": round(t_loop / t_batch, 2),

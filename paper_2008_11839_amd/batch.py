@@ -249,6 +249,34 @@ class Autotuner:
         top = max(edges, key=edges.get)
         return int(self.table[top]["choice"].get("block", 256))
 
+    @staticmethod
+    def tune_batch_block(db: "DeviceBatch", classes: list, labels: torch.Tensor,
+                         workspace: torch.Tensor, reps: int = 3) -> tuple:
+        """Workgroup shape for one batch launch, timed on the batch itself:
+        every shape in BLOCKS runs the whole batch reps times (HIP events) and
+        the fastest is kept in db.  The per-class shapes come from each class's
+        own graphs timed alone, but in the batch every class's unions run
+        beside the others'.  Returns (shape, {shape: mean ms})."""
+        times = {}
+        keep = int(db.c.block)
+        try:
+            for b in BLOCKS:
+                db.c.block = b
+                cc_batch(db, classes, labels=labels, workspace=workspace)  # warm
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    cc_batch(db, classes, labels=labels, workspace=workspace)
+                e1.record()
+                torch.cuda.synchronize()
+                times[b] = e0.elapsed_time(e1) / reps
+        finally:
+            db.c.block = keep
+        best = min(times, key=times.get)
+        db.c.block = best
+        return best, times
+
     def classes_for(self, keys: list):
         """(class option list, per-graph class index) for cc_batch."""
         uniq = sorted(set(keys))

@@ -133,6 +133,19 @@ def test_autotuner_choices_give_oracle_labels(batch_case, tmp_path):
     lab = B.cc_batch(db, classes)
     torch.cuda.synchronize()
     _check(hb, gs, want, lab)
+    # the launch shape timed on the whole batch: every shape tried, the
+    # fastest kept, labels unchanged
+    import ctypes
+    from paper_2008_11839_amd import gconn as G
+    bb = ctypes.c_size_t()
+    G._check(G.lib().gconn_cc_batch_workspace_size(ctypes.byref(db.c), ctypes.byref(bb)))
+    ws = G.alloc_workspace(bb.value)
+    block, times = B.Autotuner.tune_batch_block(db, classes, lab, ws, reps=1)
+    assert sorted(times) == sorted(B.BLOCKS) and block == min(times, key=times.get)
+    assert int(db.c.block) == block
+    lab = B.cc_batch(db, classes, workspace=ws)
+    torch.cuda.synchronize()
+    _check(hb, gs, want, lab)
     # the cached table is reused without re-timing
     again = B.Autotuner(str(tmp_path / "table.json"))
     assert again.table.keys() == tuner.table.keys()
