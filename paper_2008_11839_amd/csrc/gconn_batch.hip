@@ -232,26 +232,77 @@ __global__ void k_batch_gather(const uint64_t* __restrict__ off, uint32_t* P, ui
                                const uint8_t* __restrict__ graph_class, BatchClasses cl,
                                const uint32_t* __restrict__ lmax, Ctrl* c, WorkLists wl,
                                int want_stats) {
+  // Four consecutive vertices per lane (one tile, so one graph): their row
+  // bounds and parents are loaded together and their root walks advance in
+  // lockstep, so a wave keeps several independent loads in flight.  L is the
+  // root of the graph's largest sampled tree (k_batch_lmax walked to it and
+  // no link runs before the finish), so a walk that reaches it stops there.
+  // The work-list appends then go tile by tile, 64 consecutive vertices per
+  // append as the finish expects (its lanes read consecutive rows): lane l
+  // takes vertex 64 j + l of the wave's four tiles from the lane holding it.
   unsigned long long act = 0, edges = 0;
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    const uint32_t g = tile_graph[base >> 6];
-    const bool sampled = class_of(cl, graph_class, g).sample != 0;
-    const uint32_t L = lmax[g];
-    const uint64_t v = base + lane();
-    const uint64_t deg = off[v + 1] - off[v];
-    uint32_t r = (uint32_t)v;
-    if (sampled) {
-      const uint32_t p = P[v];
-      r = p;
-      if (p != v) {
-        r = root_plain(P, p);
-        if (r != p) P[v] = r;
+  for (uint64_t base = wave_base() * 4; base < n; base += wave_stride() * 4) {
+    const uint64_t v0 = base + 4 * lane();
+    const bool live = v0 < n;  // n is a multiple of 64: then v0 + 3 < n too
+    const uint32_t g = live ? tile_graph[v0 >> 6] : 0u;
+    const bool sampled = live && class_of(cl, graph_class, g).sample != 0;
+    const uint32_t L = live ? lmax[g] : kEmpty;
+    uint64_t o[5];
+    uint32_t p[4], r[4];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] = live ? off[v0 + j] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      p[j] = sampled ? P[v0 + j] : (uint32_t)(v0 + j);
+      r[j] = p[j];
+    }
+    bool walk[4], more = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      walk[j] = sampled && p[j] != v0 + j && p[j] != L;
+      more = more || walk[j];
+    }
+    while (more) {
+      more = false;
+      uint32_t q[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) q[j] = walk[j] ? P[r[j]] : r[j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (walk[j]) {
+          if (q[j] == r[j]) {
+            walk[j] = false;
+          } else {
+            r[j] = q[j];
+            walk[j] = q[j] != L;
+          }
+        }
+        more = more || walk[j];
       }
     }
-    const bool active = deg > 0 && r != L;
-    wl_push(wl, c, base >> 6, (uint32_t)v, deg, active);
-    act += active ? 1 : 0;
-    edges += active ? deg : 0;
+    uint32_t degs[4], act_mask = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (live && r[j] != p[j]) P[v0 + j] = r[j];
+      degs[j] = live ? (uint32_t)(o[j + 1] - o[j]) : 0u;
+      if (degs[j] > 0 && r[j] != L) act_mask |= 1u << j;
+    }
+    const uint32_t src_k = lane() & 3;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t from = 16 * t + (lane() >> 2);  // the lane holding vertex 64 t + lane
+      uint32_t d = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t x = __shfl(degs[j], from);
+        d = src_k == (uint32_t)j ? x : d;
+      }
+      const bool active = (__shfl(act_mask, from) >> src_k) & 1u;
+      const uint64_t v = base + 64 * t + lane();
+      wl_push(wl, c, (base >> 6) + t, (uint32_t)v, d, active);
+      act += active ? 1 : 0;
+      edges += active ? d : 0;
+    }
   }
   if (want_stats) {
     act = wave_sum(act);
@@ -295,13 +346,39 @@ __global__ void k_batch_finish(const uint64_t* __restrict__ off, const uint32_t*
 }
 
 // labels_out[v] = root(v) - vbase[g]: per-graph local labels.
+// Four tiles per wave step, a vertex of each per lane, their root walks in
+// lockstep; the batch's n is a multiple of 64.
 __global__ void k_batch_finalize(const uint32_t* P, uint32_t n,
                                  const uint32_t* __restrict__ tile_graph,
                                  const uint32_t* __restrict__ vbase, uint32_t* out) {
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    const uint32_t lo = vbase[tile_graph[base >> 6]];
-    const uint64_t v = base + lane();
-    out[v] = root_plain(P, (uint32_t)v) - lo;
+  const uint64_t tiles = (uint64_t)n >> 6;
+  for (uint64_t t0 = wave_index() * 4; t0 < tiles; t0 += wave_count() * 4) {
+    uint32_t lo[4], r[4];
+    uint64_t v[4];
+    bool live[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      live[j] = t0 + j < tiles;  // uniform over the wave
+      v[j] = ((t0 + j) << 6) + lane();
+      lo[j] = live[j] ? vbase[tile_graph[t0 + j]] : 0u;
+      r[j] = live[j] ? P[v[j]] : 0u;
+    }
+    bool more = true;
+    while (more) {
+      more = false;
+      uint32_t q[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) q[j] = live[j] ? P[r[j]] : r[j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (q[j] != r[j]) {
+          r[j] = q[j];
+          more = true;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (live[j]) out[v[j]] = r[j] - lo[j];
   }
 }
 
@@ -445,7 +522,7 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
     GCONN_LAUNCHED("k_batch_sample");
     k_batch_lmax<<<G, 1024, 0, s>>>(P, b->vbase, b->graph_class, cl, lmax_samples, seed, lmax);
     GCONN_LAUNCHED("k_batch_lmax");
-    k_batch_gather<<<grid_for(n, block), block, 0, s>>>(b->offsets, P, n, tiles, b->graph_class, cl,
+    k_batch_gather<<<grid_for(n / 4, block), block, 0, s>>>(b->offsets, P, n, tiles, b->graph_class, cl,
                                                       lmax, ctrl, wl, stats ? 1 : 0);
     GCONN_LAUNCHED("k_batch_gather");
     const uint32_t fgrid = persistent_grid(k_batch_finish, block);
@@ -454,7 +531,7 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
     GCONN_LAUNCHED("k_batch_finish");
   }
   if (n > 0) {
-    k_batch_finalize<<<grid_for(n, block), block, 0, s>>>(P, n, tiles, b->vbase, labels_out);
+    k_batch_finalize<<<grid_for(n / 4, block), block, 0, s>>>(P, n, tiles, b->vbase, labels_out);
     GCONN_LAUNCHED("k_batch_finalize");
   }
   if (stats) {
