@@ -152,17 +152,27 @@ __global__ void k_batch_hb1(const uint64_t* __restrict__ off, const uint32_t* __
                             uint32_t n, const uint32_t* __restrict__ tile_graph,
                             const uint8_t* __restrict__ graph_class, BatchClasses cl, uint32_t* P,
                             Ctrl* stats) {
+  // four tiles per wave step: their graphs and classes are looked up
+  // together (the lookups are uniform over the wave), then the hook-based
+  // tiles among them do their one store per vertex
   unsigned long long took = 0, linked = 0;
-  for (uint64_t base = wave_base(); base < n; base += wave_stride()) {
-    if (class_of(cl, graph_class, tile_graph[base >> 6]).sample != 2) continue;  // per tile
-    const uint64_t v = base + lane();
-    const uint64_t b = off[v];
-    if (off[v + 1] > b) {
-      ++took;
-      const uint32_t w = nbrs[b];
-      if (w < v) {
-        P[v] = w;
-        ++linked;
+  const uint64_t tiles = (uint64_t)n >> 6;  // n is a multiple of 64
+  for (uint64_t t0 = wave_index() * 4; t0 < tiles; t0 += wave_count() * 4) {
+    uint32_t g[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g[j] = t0 + j < tiles ? tile_graph[t0 + j] : 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (t0 + j >= tiles || class_of(cl, graph_class, g[j]).sample != 2) continue;  // uniform
+      const uint64_t v = ((t0 + j) << 6) + lane();
+      const uint64_t b = off[v];
+      if (off[v + 1] > b) {
+        ++took;
+        const uint32_t w = nbrs[b];
+        if (w < v) {
+          P[v] = w;
+          ++linked;
+        }
       }
     }
   }
@@ -513,7 +523,7 @@ gconn_status run_batch(const gconn_batch* b, uint32_t* labels_out, void* workspa
     bool any_hb = false;
     for (uint32_t i = 0; i < num_classes; ++i) any_hb = any_hb || cl.c[i].sample == 2;
     if (any_hb) {
-      k_batch_hb1<<<std::min<uint32_t>(grid_for(n, block), 8192), block, 0, s>>>(
+      k_batch_hb1<<<std::min<uint32_t>(grid_for(n / 4, block), 8192), block, 0, s>>>(
           b->offsets, b->nbrs, n, tiles, b->graph_class, cl, P, st);
       GCONN_LAUNCHED("k_batch_hb1");
     }
