@@ -510,7 +510,7 @@ def batched_bench(G, args) -> dict:
     total_n = sum(g.n for g in graphs)
     total_m = sum(g.m for g in graphs)
     log(f"batched workload: {len(graphs)} graphs, n={total_n} m={total_m} ({time.time() - t0:.1f}s)")
-    tuner = B.Autotuner(reps=2, per_class=2)
+    tuner = B.Autotuner(reps=5, per_class=3)
     keys = tuner.tune(graphs)
     classes, gclass = tuner.classes_for(keys)
     hb = B.concat(graphs)
