@@ -115,3 +115,34 @@ def test_bfs_bottom_up_deep_rows(gpu_available, seed):
         row = nb[off[v]:off[v + 1]]
         first = row[np.argmax(lev[row] == 1)]
         assert fu[v] == first, (v, fu[v], first)
+
+
+def test_bfs_long_diameter_mesh(gpu_available):
+    """A mesh whose BFS runs over a thousand levels: after the first batch of
+    levels the frontier stays far below the switch point, so batches enqueue
+    only the top-down kernels with grids sized to the frontier.  Labels,
+    source and forest are checked as above (every parent one level up)."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    Cg = graphgen.grid2d(1024, 256, 0.9, 3)
+    n = Cg.n
+    off = Cg.offsets.astype(np.int64)
+    nb = Cg.nbrs.astype(np.int64)
+    want = oracle.cc(n, Cg.offsets, Cg.nbrs)
+    _, src = oracle.sample_bfs(n, Cg.offsets, Cg.nbrs)
+    lev = _levels(n, off, nb, src)
+    assert lev.max() > 800  # many batches of eight levels
+    dg = G.csr(Cg.offsets, Cg.nbrs, n)
+    say(f"[bfs-mesh] n={n} m={Cg.m} levels={int(lev.max())}")
+    lab, st = G.cc(dg, options=G.Options(sample="bfs"), stats=True)
+    torch.cuda.synchronize()
+    assert st["bfs_source"] == src
+    assert st["rounds"] == int(lev.max()) + 1  # one per non-empty frontier, the source's included
+    assert np.array_equal(G.to_u32(lab), want)
+    fu, fv, lab2 = G.spanning_forest(dg, want_labels=True, options=G.Options(sample="bfs"))
+    torch.cuda.synchronize()
+    fu, fv = G.to_u32(fu).astype(np.int64), G.to_u32(fv).astype(np.int64)
+    assert np.array_equal(G.to_u32(lab2), want)
+    oracle.check_forest(n, Cg.offsets, Cg.nbrs, fu.astype(np.uint32), fv.astype(np.uint32), want)
+    reached = np.nonzero(lev > 0)[0]
+    assert np.array_equal(lev[fu[reached]], lev[reached] - 1)
