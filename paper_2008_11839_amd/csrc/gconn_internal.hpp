@@ -41,7 +41,6 @@ struct Ctrl {
   uint32_t queue_cursor;              // BFS bitmap -> queue rebuild
   uint32_t pad0;
   unsigned long long edge_count;      // materialised finish edges (SV/LT/LP)
-  unsigned long long bfs_key;         // argmax-degree key
   unsigned long long frontier_edges[2];
   unsigned long long explored_edges;
   unsigned long long stat_sampled;
@@ -76,6 +75,7 @@ struct WsLayout {
   size_t fr_bits0 = 0, fr_bits1 = 0;  // BFS frontier bitmaps
   size_t queue0 = 0, queue1 = 0;      // BFS frontier queues
   size_t bfs_stripes = 0;             // BFS per-level counter stripes
+  size_t bfs_slots = 0;               // BFS per-workgroup argmax / minimum slots
   size_t resid = 0;   // k-out pre-link: residual sampled edges (uint2[n])
   size_t words = 0;   // Union-JTB (rank, parent) words (uint64[n])
   size_t roots = 0;   // Union-JTB flat roots after sampling (uint32[n])

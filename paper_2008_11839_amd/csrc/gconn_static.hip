@@ -1622,8 +1622,46 @@ __global__ void k_lp_round(const uint32_t* __restrict__ esrc, const uint32_t* __
   block_mark_changed(c, slot, any);
 }
 
+// Workgroup partial results of the source choice (argmax of the degree) and
+// of the BFS component's minimum id: workgroup b stores its result in slot b
+// and one workgroup of kFoldThreads folds the slots, so no workgroup takes an
+// atomic on a single address (device atomics there serialise at about 11 ns
+// each, which for thousands of workgroups is most of such a kernel's time).
+constexpr uint32_t kBfsSlots = 8192;
+constexpr uint32_t kFoldThreads = 1024;
+
+// Maximum (kMax) or minimum of slots[0, nslots), nslots <= kBfsSlots, over a
+// workgroup of kFoldThreads: each thread issues its eight loads before it
+// combines them, so the fold waits about one load latency, not eight.  The
+// result is valid in thread 0; `none` is the identity.
+template <bool kMax, typename T>
+__device__ __forceinline__ T fold_slots(const T* __restrict__ slots, uint32_t nslots, T none) {
+  constexpr uint32_t kPer = kBfsSlots / kFoldThreads;
+  T v[kPer];
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t i = threadIdx.x + j * kFoldThreads;
+    v[j] = i < nslots ? slots[i] : none;
+  }
+  T x = none;
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) x = kMax ? (v[j] > x ? v[j] : x) : (v[j] < x ? v[j] : x);
+  for (int d = 32; d >= 1; d >>= 1) {
+    const T o = __shfl_xor(x, d);
+    x = kMax ? (o > x ? o : x) : (o < x ? o : x);
+  }
+  __shared__ T part[kFoldThreads / 64];
+  if (lane() == 0) part[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (uint32_t w = 1; w < kFoldThreads / 64; ++w)
+      x = kMax ? (part[w] > x ? part[w] : x) : (part[w] < x ? part[w] : x);
+  return x;
+}
+
 template <typename OffT>
-__global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) {
+__global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n,
+                             unsigned long long* __restrict__ slots) {
   // four consecutive vertices per lane: their five row bounds are loaded
   // together, so a lane's iterations are not one dependent load each
   unsigned long long best = 0;
@@ -1642,15 +1680,14 @@ __global__ void k_bfs_argmax(const OffT* __restrict__ off, uint32_t n, Ctrl* c) 
     }
   }
   // every lane of a wave ran the same iterations, so all are active here;
-  // then the workgroup's waves combine in LDS: one atomic per workgroup (the
-  // key is a single address, where device atomics serialise at ~11 ns each)
+  // then the workgroup's waves combine in LDS into the workgroup's slot
   __shared__ unsigned long long wmax[16];
   best = wave_max(best);
   if (lane() == 0) wmax[threadIdx.x >> 6] = best;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (uint32_t w = 1; w < (blockDim.x + 63) / 64; ++w) best = wmax[w] > best ? wmax[w] : best;
-    if (best) atomicMax(&c->bfs_key, best);
+    slots[blockIdx.x] = best;
   }
 }
 
@@ -1688,12 +1725,17 @@ __device__ __forceinline__ void bfs_stripe_add(BfsStripe* st, uint32_t level_slo
   }
 }
 
+// Launched with one workgroup of kFoldThreads: folds the argmax slots of the
+// `nslots` workgroups of k_bfs_argmax into the source and seeds the first
+// frontier.
 template <typename OffT>
-__global__ void k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* visited,
-                            uint32_t* queue0, BfsStripe* st) {
+__global__ void __launch_bounds__(kFoldThreads)
+    k_bfs_start(const OffT* __restrict__ off, Ctrl* c, uint32_t* visited, uint32_t* queue0,
+                BfsStripe* st, const unsigned long long* __restrict__ slots, uint32_t nslots) {
   for (uint32_t i = threadIdx.x; i < 2 * kBfsStripes; i += blockDim.x) st[i].count = st[i].edges = 0;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    uint32_t s = (uint32_t)(0xFFFFFFFFull - (c->bfs_key & 0xFFFFFFFFull));
+  const unsigned long long key = fold_slots<true>(slots, nslots, 0ull);
+  if (threadIdx.x == 0) {
+    uint32_t s = (uint32_t)(0xFFFFFFFFull - (key & 0xFFFFFFFFull));
     c->bfs_source = s;
     visited[s >> 5] |= 1u << (s & 31);
     queue0[0] = s;
@@ -2136,9 +2178,10 @@ k_bfs_bu(const OffT* __restrict__ off, const uint32_t* __restrict__ nbrs, uint32
 
 // Re-root the BFS component at its minimum id (the BFS labels reached vertices
 // with the source, which is not the component minimum).
-__global__ void k_bfs_min(const uint32_t* __restrict__ visited, uint32_t words, Ctrl* c) {
+__global__ void k_bfs_min(const uint32_t* __restrict__ visited, uint32_t words,
+                          uint32_t* __restrict__ slots) {
   // the first visited id of the lane's words, then of the wave and the
-  // workgroup: one atomic per workgroup on the single-address minimum
+  // workgroup, stored in the workgroup's slot
   uint32_t best = kEmpty;
   for (uint64_t base = wave_base(); base < words; base += wave_stride()) {
     const uint64_t i = base + lane();
@@ -2157,8 +2200,16 @@ __global__ void k_bfs_min(const uint32_t* __restrict__ visited, uint32_t words, 
   __syncthreads();
   if (threadIdx.x == 0) {
     for (uint32_t w = 1; w < (blockDim.x + 63) / 64; ++w) best = wmin[w] < best ? wmin[w] : best;
-    if (best != kEmpty) atomicMin(&c->comp_min, best);
+    slots[blockIdx.x] = best;
   }
+}
+
+// One workgroup of kFoldThreads folds the `nslots` slots of k_bfs_min into
+// the component minimum.
+__global__ void __launch_bounds__(kFoldThreads)
+    k_bfs_min_fold(const uint32_t* __restrict__ slots, uint32_t nslots, Ctrl* c) {
+  const uint32_t best = fold_slots<false>(slots, nslots, kEmpty);
+  if (threadIdx.x == 0) c->comp_min = best;
 }
 
 // Every slot is written, four per lane: a visited vertex gets the component
@@ -2643,11 +2694,13 @@ struct Run {
                           reinterpret_cast<uint32_t*>(ws + L.queue1)};
     k_fill<<<gridN(words), block, 0, s>>>(visited, 0u, words);
     GCONN_LAUNCHED("k_fill(visited)");
-    k_bfs_argmax<OffT><<<std::min<uint32_t>(gridN((n + 3) / 4), 2048), block, 0, s>>>(off, n,
-                                                                                     ctrl);
+    unsigned long long* key_slots = reinterpret_cast<unsigned long long*>(ws + L.bfs_slots);
+    const uint32_t argmax_grid = std::min<uint32_t>(gridN((n + 3) / 4), kBfsSlots);
+    k_bfs_argmax<OffT><<<argmax_grid, block, 0, s>>>(off, n, key_slots);
     GCONN_LAUNCHED("k_bfs_argmax");
     BfsStripe* stripes = reinterpret_cast<BfsStripe*>(ws + L.bfs_stripes);
-    k_bfs_start<OffT><<<1, 64, 0, s>>>(off, ctrl, visited, queue[0], stripes);
+    k_bfs_start<OffT><<<1, kFoldThreads, 0, s>>>(off, ctrl, visited, queue[0], stripes,
+                                                 key_slots, argmax_grid);
     GCONN_LAUNCHED("k_bfs_start");
     // Levels run kRoundsPerSync at a time between host checks: each level's
     // direction and representation changes are decided on the device
@@ -2726,8 +2779,13 @@ struct Run {
       GCONN_HIP(hipStreamSynchronize(s));
       rounds = levels;
     }
-    k_bfs_min<<<std::min<uint32_t>(gridN(words), 1024), block, 0, s>>>(visited, words, ctrl);
+    // the argmax slots are free again: the minimum's slots reuse them
+    uint32_t* min_slots = reinterpret_cast<uint32_t*>(ws + L.bfs_slots);
+    const uint32_t min_grid = std::min<uint32_t>(gridN(words), kBfsSlots);
+    k_bfs_min<<<min_grid, block, 0, s>>>(visited, words, min_slots);
     GCONN_LAUNCHED("k_bfs_min");
+    k_bfs_min_fold<<<1, kFoldThreads, 0, s>>>(min_slots, min_grid, ctrl);
+    GCONN_LAUNCHED("k_bfs_min_fold");
     k_bfs_label<<<gridN((n + 3) / 4), block, 0, s>>>(visited, n, ctrl, P);
     GCONN_LAUNCHED("k_bfs_label");
     // the work lists were used as scratch: clear their counters
@@ -3103,6 +3161,7 @@ WsLayout plan_workspace(const gconn_graph& g, const gconn_options& o, bool fores
     L.queue0 = take(4 * n);
     L.queue1 = take(4 * n);
     L.bfs_stripes = take(2 * kBfsStripes * sizeof(BfsStripe));
+    L.bfs_slots = take(kBfsSlots * sizeof(unsigned long long));
   }
   L.total = at;
   return L;
