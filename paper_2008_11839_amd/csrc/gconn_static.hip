@@ -2757,7 +2757,12 @@ struct Run {
       GCONN_HIP(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
       GCONN_HIP(hipStreamSynchronize(s));
       const uint32_t mode = h.bfs_mode;
-      if (mode == 0) break;
+      if (mode == 0) {
+        // the copy followed every kernel of the last batch, so the level
+        // count in it is final
+        rounds = h.bfs_levels;
+        break;
+      }
       const uint64_t unexplored = g.m > h.explored_edges ? g.m - h.explored_edges : 0;
       td_only = mode == 1 && h.bfs_as_queue != 0 &&
                 (unsigned __int128)h.frontier_edges[next] * 14 * 64 <= unexplored;
@@ -2771,13 +2776,6 @@ struct Run {
       }
       if (level + kRoundsPerSync > (uint64_t)n + kRoundsPerSync)
         return fail(GCONN_EDEVICE, "BFS did not finish within n levels");
-    }
-    {
-      uint32_t levels = 0;
-      GCONN_HIP(hipMemcpyAsync(&levels, &ctrl->bfs_levels, sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, s));
-      GCONN_HIP(hipStreamSynchronize(s));
-      rounds = levels;
     }
     // the argmax slots are free again: the minimum's slots reuse them
     uint32_t* min_slots = reinterpret_cast<uint32_t*>(ws + L.bfs_slots);
