@@ -146,3 +146,33 @@ def test_bfs_long_diameter_mesh(gpu_available):
     oracle.check_forest(n, Cg.offsets, Cg.nbrs, fu.astype(np.uint32), fv.astype(np.uint32), want)
     reached = np.nonzero(lev > 0)[0]
     assert np.array_equal(lev[fu[reached]], lev[reached] - 1)
+
+
+def test_bfs_source_and_minimum_past_the_first_pass(gpu_available):
+    """More vertices than one grid-stride pass of the source-selection kernel
+    covers (its grid stops at 8,192 workgroups, 8,388,608 vertices with
+    256-thread workgroups of four vertices per lane), with the two
+    largest-degree vertices tied at degree 100 and both beyond that first
+    pass: the source is the smaller id of the two.  The source's component
+    also holds vertex 5, so its minimum comes from another workgroup's slot
+    than the source's, and every other vertex keeps its own id or joins the
+    second hub's or the third hub's (degree 99) component."""
+    import torch
+    from paper_2008_11839_amd import gconn as G
+    n = 9_000_005
+    hub_a, hub_b, hub_c = 8_500_000, 8_999_990, 3
+    pairs = [(hub_a, 8_400_000 + i) for i in range(100)]
+    pairs += [(hub_b, 8_800_000 + i) for i in range(100)]
+    pairs += [(hub_c, 100 + i) for i in range(99)]
+    pairs += [(8_400_050, 5)]
+    Cg = graphgen.from_pairs(n, pairs, "two_tied_hubs")
+    want = oracle.cc(n, Cg.offsets, Cg.nbrs)
+    _, src = oracle.sample_bfs(n, Cg.offsets, Cg.nbrs)
+    assert src == hub_a and want[hub_a] == 5 and want[hub_b] == 8_800_000
+    dg = G.csr(Cg.offsets, Cg.nbrs, n)
+    say(f"[bfs-tied-hubs] n={n} m={Cg.m}")
+    lab, st = G.cc(dg, options=G.Options(sample="bfs"), stats=True)
+    torch.cuda.synchronize()
+    assert st["bfs_source"] == src
+    assert st["rounds"] == 3  # frontiers {hub}, its leaves, {5}
+    assert np.array_equal(G.to_u32(lab), want)
